@@ -1,0 +1,237 @@
+"""Benchmark of the Chebyshev-filter hot path on one MI355X.
+
+Workload: the medium synthetic cluster (96^3 grid, h = 0.4 bohr, 16 atoms with
+4 Kleinman-Bylander projectors each, 64 orbitals N(0,1), degree m = 24,
+stencil order 12).  One step is one filtered-subspace pass over the resident
+orbital block: 40-step FP64 Lanczos bounds on the device, the Chebyshev filter
+in the selected dtype, FP64 Rayleigh-Ritz on the device and the subspace
+rotation.  ``value`` is filtered orbital*gridpoint updates per second of the
+whole step (N_d * N_s * m / step time).
+
+Prints ONE JSON line (rank 0).  Defaults: 1 GPU, 10 timed steps, 3 warmup.
+Modes: --dtype f32 (default; FP64 also measured and reported beside it) or f64.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KSTEPS_LANCZOS = 40
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic_cluster96.txt")
+STENCIL_SRC = os.path.join(ROOT, "paper_1603_04334_amd", "csrc", "stencil.hip")
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--dtype", choices=["f32", "f64"], default="f32")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-fp64-compare", action="store_true")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="run only a plain device copy of known size (for counter calibration)")
+    return p.parse_args()
+
+
+def source_hash() -> str:
+    return hashlib.sha256(open(STENCIL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per step-kernel launch from committed counter runs, or None
+    when absent or taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("stencil_sha256_16") != source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 28  # 256 Mi floats = 1 GiB read + 1 GiB written
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 5}))
+
+
+class Pass:
+    """Resident state of one workload and one dtype."""
+
+    def __init__(self, case, cluster, dtype):
+        import torch
+        from paper_1603_04334_amd import binding, inputs
+        self.binding = binding
+        self.case = case
+        self.cl = cluster
+        self.dt = torch.float32 if dtype == "f32" else torch.float64
+        self.code = binding.SPARC_F32 if dtype == "f32" else binding.SPARC_F64
+        self.op = binding.Operator(cluster)
+        X = inputs.orbitals(cluster.nd, case.ns, case.seed)
+        self.X = torch.from_numpy(X).to(self.dt).cuda()
+        del X
+        self.Y = torch.empty_like(self.X)
+        self.R = torch.empty_like(self.X)
+        self.v0 = torch.from_numpy(inputs.lanczos_start(cluster.nd, case.seed)).cuda()
+        self.ws = self.op.workspace(self.code, case.ns, 1)
+        self.ub = self.op.upper_bound()
+        self.bounds = None
+        self.ritz = None
+
+    def step(self, profile_filter=False):
+        b = self.binding
+        _, _, theta = self.op.lanczos(KSTEPS_LANCZOS, self.v0)
+        a0, a, bb = b.select_bounds(theta, 8, ubound=self.ub)
+        self.bounds = (a0, a, bb)
+        if profile_filter:
+            b.profile.enable(True)
+        self.op.cheb_filter(self.X, self.case.m, a0, a, bb, Y=self.Y, ws=self.ws)
+        if profile_filter:
+            b.profile.enable(False)
+        self.ritz, Qt = self.op.rayleigh_ritz(self.Y)
+        b.rotate(self.Y, Qt, out=self.R)
+
+    def filter_only(self):
+        a0, a, bb = self.bounds
+        self.op.cheb_filter(self.X, self.case.m, a0, a, bb, Y=self.Y, ws=self.ws)
+
+
+def timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def alg_bytes_per_step_launch(case, cl, s):
+    """Algorithmic HBM bytes of the fused step kernel averaged over one filter:
+    the first step reads X and writes Y_1; each later step reads Y_k and
+    Y_{k-1} and writes Y_{k+1}; plus one read of V_eff and of the projector
+    values per step."""
+    nd, ns, m = cl.nd, case.ns, case.m
+    streams = (2 + 3 * (m - 1)) / m
+    chi = sum(a.chi.size for a in cl.atoms)
+    return streams * s * nd * ns + s * nd + s * chi
+
+
+def cpu_baseline(case, cl):
+    import oracle
+    from paper_1603_04334_amd import inputs
+    cols = list(range(8))
+    X = inputs.orbitals(cl.nd, case.ns, case.seed, cols=cols)
+    a0, a, b = -2.0, 3.0, oracle.upper_bound(cl)
+    t0 = time.perf_counter()
+    oracle.cheb_filter(cl, X, case.m, a0, a, b)
+    dt = time.perf_counter() - t0
+    return {"value": len(cols) * cl.nd * case.m / dt, "unit": "orbital*gridpts/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"FP64 C oracle Chebyshev filter (degree {case.m}) of {len(cols)} of the {case.ns} "
+                      f"orbitals of the same cluster, {dt:.1f} s on the host"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    from paper_1603_04334_amd import binding, inputs
+    binding.lib()
+    case = inputs.MEDIUM
+    cl = inputs.case_cluster(case.name)
+    s = 4 if args.dtype == "f32" else 8
+
+    main_pass = Pass(case, cl, args.dtype)
+    # timed region: K whole steps
+    t_step = timed(main_pass.step, args.steps, args.warmup)
+    updates = cl.nd * case.ns * case.m
+    # kernel timing: the same steps again with per-launch events on the filter's kernels
+    binding.profile.reset()
+    torch.cuda.synchronize()
+    for _ in range(args.steps):
+        main_pass.step(profile_filter=True)
+    torch.cuda.synchronize()
+    n_launch, ms = binding.profile.read(0)
+    n_g, ms_g = binding.profile.read(1)
+    binding.profile.reset()
+    avg_s = ms / 1e3 / max(n_launch, 1)
+    alg = alg_bytes_per_step_launch(case, cl, s)
+    achieved = alg / avg_s / 1e9
+    traffic = read_traffic() if args.dtype == "f32" else None
+    t_filter = timed(main_pass.filter_only, args.steps, 1)
+
+    out = {
+        "metric": "filtered orbital*gridpts/s",
+        "value": updates / t_step,
+        "unit": "orbital*gridpts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": case.name, "grid": [case.n] * 3, "h": case.h, "atoms": case.natoms,
+                   "projectors_per_atom": (case.lmax + 1) ** 2, "orbitals": case.ns, "degree": case.m,
+                   "stencil_radius": 6, "step": "lanczos40_fp64+cheb_filter+rayleigh_ritz_fp64+rotation",
+                   "parallelism": "single_gpu"},
+        "filter_only": {"value": updates / t_filter, "ms": t_filter * 1e3},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "step_kernel (fused stencil+V+nonlocal scatter+recurrence)",
+                     "launches": n_launch, "avg_launch_us": avg_s * 1e6,
+                     "alg_bytes_per_launch": alg},
+        "gather_kernel": {"launches": n_g, "avg_launch_us": ms_g / max(n_g, 1) * 1e3},
+        "bounds": list(main_pass.bounds),
+    }
+    tz, ty, cx = main_pass.op.step_config(main_pass.code, case.ns)
+    out["config"]["tile"] = {"z": tz, "y": ty, "chunk_x": cx}
+    if not args.no_fp64_compare and args.dtype == "f32":
+        del main_pass
+        torch.cuda.empty_cache()
+        p64 = Pass(case, cl, "f64")
+        t64 = timed(p64.step, args.steps, args.warmup)
+        t64f = timed(p64.filter_only, args.steps, 1)
+        out["fp64"] = {"value": updates / t64, "ms_per_step": t64 * 1e3, "filter_only": updates / t64f,
+                       "filter_ms": t64f * 1e3}
+        del p64
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case, cl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

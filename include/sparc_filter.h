@@ -1,0 +1,217 @@
+/*
+ * sparc_filter.h -- C ABI of the MI355X Chebyshev-filter library.
+ *
+ * The library applies the discrete Kohn-Sham Hamiltonian of a real-space,
+ * finite-difference isolated-cluster calculation and the Chebyshev polynomial
+ * filter of the filtered subspace iteration built on it, following Ghosh &
+ * Suryanarayana, "SPARC ... Part I: Isolated clusters" (arXiv:1603.04334):
+ *
+ *   H = -1/2 lap_h + diag(V_eff) + V_nl                         (Sec. 2, Eq. EL)
+ *   lap_h f = sum_{p=0..n_o} w_p (six values at distance p)     (Sec. 3.1, Eq. FD:Laplacian)
+ *   w_p as in Sec. 3.1 Eq. weightsLap; f = 0 off the grid      (zero Dirichlet, Sec. 3.1)
+ *   V_nl f = h^3 sum_J sum_lm gamma_Jl chi_Jlm chi_Jlm^T f      (Sec. 3.1, Eq. non-localPS:FD)
+ *   Psi_f = p_m(H) Psi,  p_m(t) = C_m((t - c)/e)                (Sec. 3.4, Eq. ChebFilter, Alg. 2)
+ *   H_s = Psi_f^T H Psi_f, M_s = Psi_f^T Psi_f, H_s y = l M_s y (Sec. 3.4, Eq. SubspaceGeneralizedEigenproblem)
+ *   Psi = Psi_f Y                                               (Sec. 3.4, Eq. OrbitalTransformation)
+ *
+ * Conventions shared by every call:
+ *   - Grid: n[0] x n[1] x n[2] nodes (x, y, z); linear node index
+ *     k + n[2]*(j + n[1]*i), z fastest.  N_d = n[0]*n[1]*n[2].
+ *   - Orbital blocks are dense N_d x ns matrices in column-major order (the
+ *     orbitals are the columns, Sec. 3.1): column c starts at element c*ld,
+ *     ld >= N_d.  They live in device memory owned by the caller.
+ *   - dtype selects the storage and arithmetic type of an orbital block:
+ *     SPARC_F64 (double) or SPARC_F32 (float, FP32 accumulation; filter
+ *     coefficients are computed in FP64 and rounded once).
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *     is enqueued on it and the call returns; results are valid once the
+ *     stream has reached that point.  Calls documented as synchronous wait.
+ *   - Workspace: calls that need scratch memory take a caller-owned device
+ *     buffer ws of at least the size returned by the matching *_bytes query.
+ *     Concurrent calls need distinct workspaces.
+ *   - Units are Hartree and bohr.
+ *   - Every call returns a sparc_status; on failure nothing has been enqueued
+ *     and sparc_last_error() gives a message for the calling thread.
+ */
+#ifndef SPARC_FILTER_H
+#define SPARC_FILTER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPARC_OK = 0,
+    SPARC_PENDING = 1,       /* job not finished (poll)                          */
+    SPARC_E_ARG = -1,        /* null pointer, bad enum, bad count                */
+    SPARC_E_SHAPE = -2,      /* grid / box / leading dimension inconsistent      */
+    SPARC_E_BOUNDS = -3,     /* filter bounds not a0 < a < b, or m < 1           */
+    SPARC_E_NOMEM = -4,      /* device allocation failed / budget exceeded       */
+    SPARC_E_HIP = -5,        /* a HIP runtime or library call failed             */
+    SPARC_E_BUSY = -6,       /* server queue full                                */
+    SPARC_E_TICKET = -7,     /* unknown ticket                                   */
+    SPARC_E_JOB = -8,        /* job failed (see sparc_job_result.status)         */
+    SPARC_E_WORKSPACE = -9,  /* workspace missing or too small                   */
+    SPARC_E_BREAKDOWN = -10, /* Lanczos reached an invariant subspace            */
+    SPARC_E_ALIAS = -11      /* input and output / workspace overlap             */
+} sparc_status;
+
+typedef enum { SPARC_F64 = 0, SPARC_F32 = 1 } sparc_dtype;
+
+/* Uniform finite-difference grid of Sec. 3.1: n nodes per axis, spacing h,
+ * stencil half-width radius = n_o (1..6; the paper uses 6). */
+typedef struct {
+    int32_t n[3];
+    double h;
+    int32_t radius;
+} sparc_grid;
+
+/* One atom's Kleinman-Bylander projectors (Sec. 2 Eq. V_nl, Sec. 3.1 Eq.
+ * non-localPS:FD), restricted to a cube of nodes (Sec. 3.2 uses cubes around
+ * atoms).  lo: first node index of the cube per axis (0-based); ext: cube
+ * extent per axis; the cube must lie inside the grid.  chi: host array of
+ * nproj*ext[0]*ext[1]*ext[2] values, projector slowest then x, y, z fastest;
+ * the h^3 quadrature weight is NOT folded in.  gamma: host array of nproj
+ * projector energies (gamma_Jl repeated over m).  1 <= nproj <= 16.  Both
+ * arrays are copied by sparc_op_create. */
+typedef struct {
+    int32_t lo[3];
+    int32_t ext[3];
+    int32_t nproj;
+    const double *chi;
+    const double *gamma;
+} sparc_atom;
+
+typedef struct sparc_op sparc_op;
+
+/* ------------------------------------------------------------------ operator */
+
+/* Build the discrete Hamiltonian of one cluster on the current HIP device.
+ * veff: host array of N_d values of V_eff at the nodes.  The op keeps device
+ * copies of V_eff and chi in FP64 and FP32, the per-tile atom lists of the
+ * fused kernel, and nothing else; it is immutable afterwards and may be used
+ * from several streams at once.  Synchronous.
+ * Errors: SPARC_E_ARG (null pointers, natoms < 0, nproj outside 1..16),
+ * SPARC_E_SHAPE (n < 1, h <= 0, radius outside 1..6, cube outside the grid),
+ * SPARC_E_NOMEM, SPARC_E_HIP. */
+int sparc_op_create(const sparc_grid *grid, const double *veff, int32_t natoms,
+                    const sparc_atom *atoms, sparc_op **out);
+
+/* Release the op's device memory.  The caller must make sure no enqueued work
+ * still uses it.  NULL is accepted. */
+int sparc_op_destroy(sparc_op *op);
+
+/* N_d of the op's grid, and the total number of projectors. */
+int64_t sparc_op_nd(const sparc_op *op);
+int32_t sparc_op_nproj(const sparc_op *op);
+
+/* Workspace in bytes needed by sparc_h_apply (which = 0) or by
+ * sparc_cheb_filter (which = 1) for ns columns of the given dtype. */
+size_t sparc_workspace_bytes(const sparc_op *op, int32_t dtype, int32_t ns, int32_t which);
+
+/* Y = H X for ns columns (Sec. 2 Eq. EL operator discretised as in Sec. 3.1).
+ * X (ldx) and Y (ldy) are device blocks of the given dtype and must not
+ * overlap.  ws: device workspace of sparc_workspace_bytes(op, dtype, ns, 0)
+ * bytes (may be NULL when the op has no atoms).  Asynchronous.
+ * Errors: SPARC_E_ARG, SPARC_E_SHAPE (ld < N_d, ns < 1), SPARC_E_ALIAS,
+ * SPARC_E_WORKSPACE, SPARC_E_HIP. */
+int sparc_h_apply(const sparc_op *op, int32_t dtype, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                  int32_t ns, void *ws, size_t ws_bytes, void *stream);
+
+/* Chebyshev filter of degree m (Sec. 3.4, Eq. ChebFilter and Alg. 2) in the
+ * scaled three-term form of the filtered subspace iteration the paper cites:
+ *   e = (b - a)/2, c = (b + a)/2, sigma_1 = e/(a0 - c), tau = 2/sigma_1,
+ *   Y_1 = (sigma_1/e)(H - cI)X,
+ *   Y_{k+1} = (2 sigma_{k+1}/e)(H - cI)Y_k - sigma_k sigma_{k+1} Y_{k-1},
+ *   sigma_{k+1} = 1/(tau - sigma_k),  k = 1..m-1,
+ * so Y = C_m((H - c)/e) X / C_m((a0 - c)/e): eigencomponents in [a, b] are
+ * damped and the component at a0 passes with gain 1.
+ * a0 plays lambda_1, a the cutoff lambda_c and b lambda_{N_d} of Alg. 2.
+ * X (ldx) is read only; Y (ldy) receives the result; neither may overlap the
+ * other or ws.  ws: sparc_workspace_bytes(op, dtype, ns, 1) bytes.
+ * Asynchronous: 2m kernel launches (m when the op has no atoms).
+ * Errors: SPARC_E_BOUNDS (m < 1 or not a0 < a < b), SPARC_E_ARG,
+ * SPARC_E_SHAPE, SPARC_E_ALIAS, SPARC_E_WORKSPACE, SPARC_E_HIP. */
+int sparc_cheb_filter(const sparc_op *op, int32_t dtype, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                      int32_t ns, int32_t m, double a0, double a, double b, void *ws, size_t ws_bytes,
+                      void *stream);
+
+/* --------------------------------------------------------- spectral bounds */
+
+/* Workspace bytes of sparc_lanczos for k steps. */
+size_t sparc_lanczos_workspace_bytes(const sparc_op *op, int32_t k);
+
+/* k steps of Lanczos on H in FP64 on the device (Sec. 4: extremal eigenvalues
+ * of H by a few Lanczos iterations), with full re-orthogonalisation (classical
+ * Gram-Schmidt applied twice per step).  v0: device FP64 start vector of N_d
+ * values (normalised internally, not modified).  Outputs on the host: alpha[k]
+ * and beta[k-1] (the tridiagonal T_k, may be NULL) and theta[k], the
+ * eigenvalues of T_k in ascending order.  Synchronous (waits for stream).
+ * Errors: SPARC_E_ARG (k < 1 or k > N_d), SPARC_E_WORKSPACE,
+ * SPARC_E_BREAKDOWN (a beta_j vanished), SPARC_E_HIP. */
+int sparc_lanczos(const sparc_op *op, int32_t k, const double *v0, double *alpha, double *beta,
+                  double *theta, void *ws, size_t ws_bytes, void *stream);
+
+/* Guaranteed upper bound on the largest eigenvalue of H: three times the
+ * maximum of the 1D stencil symbol of -1/2 lap_h, plus max V_eff, plus
+ * h^3 max(gamma_J,0) trace(chi_J^T chi_J) per atom.  Host only. */
+int sparc_upper_bound(const sparc_op *op, double *ub);
+
+/* Filter bounds from ascending Ritz values theta[k]: a0 = theta[0],
+ * a = theta[nwant-1] + shift, b = bfactor*theta[k-1], and b is lowered to
+ * ubound when ubound < b (pass ubound <= 0 to skip).
+ * Errors: SPARC_E_ARG, SPARC_E_BOUNDS (result not a0 < a < b).  Host only. */
+int sparc_select_bounds(const double *theta, int32_t k, int32_t nwant, double shift, double bfactor,
+                        double ubound, double *a0, double *a, double *b);
+
+/* ------------------------------------------------------- Rayleigh-Ritz step */
+
+/* Workspace bytes of sparc_rayleigh_ritz for ns columns of the given dtype. */
+size_t sparc_rr_workspace_bytes(const sparc_op *op, int32_t dtype, int32_t ns);
+
+/* Rayleigh-Ritz on the filtered block (Sec. 3.4): with Y promoted to FP64,
+ * H_s = Y^T (H Y) and M_s = Y^T Y (the h^3 factors cancel), then the
+ * symmetric-definite problem H_s q = theta M_s q, all in FP64 on the device.
+ * theta: host array of ns Ritz values, ascending.  evec: optional device FP64
+ * ns x ns column-major array receiving the M_s-orthonormal eigenvectors (the
+ * rotation matrix of Eq. OrbitalTransformation).  Synchronous.
+ * Errors: SPARC_E_ARG, SPARC_E_SHAPE, SPARC_E_WORKSPACE, SPARC_E_HIP
+ * (including a singular M_s reported by the eigensolver). */
+int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_t ldy, int32_t ns,
+                        double *theta, double *evec, void *ws, size_t ws_bytes, void *stream);
+
+/* Subspace rotation Psi = Psi_f Q (Sec. 3.4, Eq. OrbitalTransformation):
+ * Y (ldy) is an nd x ns block of the given dtype, Q an FP64 ns x ns
+ * column-major device matrix (converted to dtype first when dtype is F32;
+ * ws must then hold ns*ns floats, else ws may be NULL), out (ldo) an nd x ns
+ * block of dtype that must not overlap Y.  Asynchronous. */
+int sparc_rotate(int32_t dtype, const void *Y, int64_t ldy, int64_t nd, int32_t ns, const double *Q,
+                 void *out, int64_t ldo, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------- diagnostics */
+
+const char *sparc_status_str(int status);
+const char *sparc_last_error(void);
+
+/* Per-kernel timing with HIP events recorded around each launch on the
+ * launching stream.  kernel: 0 = fused stencil/recurrence step, 1 = projector
+ * gather.  enable(1) starts recording; read() synchronises the recorded
+ * events and returns the number of launches and their summed duration in ms;
+ * reset() clears the counts. */
+int sparc_profile_enable(int32_t on);
+int sparc_profile_read(int32_t kernel, int64_t *launches, double *total_ms);
+int sparc_profile_reset(void);
+
+/* Launch configuration of the fused step kernel for a dtype and ns: tile
+ * extent along z and y and the x-chunk length, as chosen by the library for
+ * the op (out parameters may be NULL). */
+int sparc_step_config(const sparc_op *op, int32_t dtype, int32_t ns, int32_t *tile_z, int32_t *tile_y,
+                      int32_t *chunk_x);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPARC_FILTER_H */

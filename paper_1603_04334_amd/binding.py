@@ -1,0 +1,303 @@
+"""ctypes binding of libsparcfilter.so.
+
+Argument marshalling only: every computation happens in the HIP library.
+The raw entry points keep the C names (``sparc_h_apply`` ...); ``Operator``
+wraps an op handle and turns torch device tensors into pointers, leading
+dimensions and the current HIP stream.  Orbital blocks are torch tensors of
+shape (ns, ld>=N_d) on the GPU: row c is orbital c, i.e. the column-major
+N_d x ns block of the C ABI with leading dimension ``X.stride(0)``.
+
+If the library has not been built this module raises on use; there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsparcfilter.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "sparc_filter.h")
+
+SPARC_OK, SPARC_PENDING = 0, 1
+SPARC_E_ARG, SPARC_E_SHAPE, SPARC_E_BOUNDS, SPARC_E_NOMEM, SPARC_E_HIP = -1, -2, -3, -4, -5
+SPARC_E_BUSY, SPARC_E_TICKET, SPARC_E_JOB, SPARC_E_WORKSPACE, SPARC_E_BREAKDOWN, SPARC_E_ALIAS = -6, -7, -8, -9, -10, -11
+SPARC_F64, SPARC_F32 = 0, 1
+
+
+class SparcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class sparc_grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("h", ctypes.c_double), ("radius", ctypes.c_int32)]
+
+
+class sparc_atom(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_int32 * 3), ("ext", ctypes.c_int32 * 3), ("nproj", ctypes.c_int32),
+                ("chi", ctypes.POINTER(ctypes.c_double)), ("gamma", ctypes.POINTER(ctypes.c_double))]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_sz = ctypes.c_size_t
+_dbl = ctypes.c_double
+_dp = ctypes.POINTER(ctypes.c_double)
+
+_SIGS = {
+    "sparc_op_create": (_i32, [ctypes.POINTER(sparc_grid), _dp, _i32, ctypes.POINTER(sparc_atom), ctypes.POINTER(_vp)]),
+    "sparc_op_destroy": (_i32, [_vp]),
+    "sparc_op_nd": (_i64, [_vp]),
+    "sparc_op_nproj": (_i32, [_vp]),
+    "sparc_workspace_bytes": (_sz, [_vp, _i32, _i32, _i32]),
+    "sparc_h_apply": (_i32, [_vp, _i32, _vp, _i64, _vp, _i64, _i32, _vp, _sz, _vp]),
+    "sparc_cheb_filter": (_i32, [_vp, _i32, _vp, _i64, _vp, _i64, _i32, _i32, _dbl, _dbl, _dbl, _vp, _sz, _vp]),
+    "sparc_lanczos_workspace_bytes": (_sz, [_vp, _i32]),
+    "sparc_lanczos": (_i32, [_vp, _i32, _vp, _dp, _dp, _dp, _vp, _sz, _vp]),
+    "sparc_upper_bound": (_i32, [_vp, _dp]),
+    "sparc_select_bounds": (_i32, [_dp, _i32, _i32, _dbl, _dbl, _dbl, _dp, _dp, _dp]),
+    "sparc_rr_workspace_bytes": (_sz, [_vp, _i32, _i32]),
+    "sparc_rayleigh_ritz": (_i32, [_vp, _i32, _vp, _i64, _i32, _dp, _vp, _vp, _sz, _vp]),
+    "sparc_rotate": (_i32, [_i32, _vp, _i64, _i64, _i32, _vp, _vp, _i64, _vp, _sz, _vp]),
+    "sparc_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "sparc_last_error": (ctypes.c_char_p, []),
+    "sparc_profile_enable": (_i32, [_i32]),
+    "sparc_profile_read": (_i32, [_i32, ctypes.POINTER(_i64), _dp]),
+    "sparc_profile_reset": (_i32, []),
+    "sparc_step_config": (_i32, [_vp, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+}
+
+
+def lib():
+    """Load libsparcfilter.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(the HIP library is required; there is no fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def header_symbols() -> Sequence[str]:
+    """Names of the functions declared in include/sparc_filter.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sparc_[a-z0-9_]+)\s*\(", text)))
+
+
+def check(status: int, what: str = "") -> int:
+    if status < 0:
+        msg = lib().sparc_last_error().decode(errors="replace")
+        raise SparcError(status, f"{what}: {msg}" if what else msg)
+    return status
+
+
+# ----------------------------------------------------------------------------- raw entry points
+
+def _fn(name):
+    def call(*args):
+        return getattr(lib(), name)(*args)
+    call.__name__ = name
+    return call
+
+
+for _name in _SIGS:
+    globals()[_name] = _fn(_name)
+
+
+# ----------------------------------------------------------------------------- convenience wrapper
+
+def _ptr(t) -> int:
+    return int(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(int(s.cuda_stream))
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return SPARC_F64
+    if t.dtype == torch.float32:
+        return SPARC_F32
+    raise TypeError("orbital blocks must be float64 or float32")
+
+
+def _block(t, nd: int, name: str):
+    if t.dim() != 2 or t.shape[1] != nd or t.stride(1) != 1:
+        raise ValueError(f"{name} must have shape (ns, nd={nd}) with unit stride along nd")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    return t.shape[0], t.stride(0)
+
+
+class Operator:
+    """An op handle built from an ``inputs.Cluster``."""
+
+    def __init__(self, cluster):
+        self.cluster = cluster
+        g = sparc_grid()
+        g.n[:] = list(cluster.n)
+        g.h = cluster.h
+        g.radius = cluster.radius
+        self._keep = []
+        atoms = (sparc_atom * max(1, len(cluster.atoms)))()
+        for i, a in enumerate(cluster.atoms):
+            chi = np.ascontiguousarray(a.chi, dtype=np.float64).reshape(-1)
+            gam = np.ascontiguousarray(a.gamma, dtype=np.float64)
+            self._keep += [chi, gam]
+            atoms[i].lo[:] = list(a.lo)
+            atoms[i].ext[:] = list(a.ext)
+            atoms[i].nproj = a.chi.shape[0]
+            atoms[i].chi = chi.ctypes.data_as(_dp)
+            atoms[i].gamma = gam.ctypes.data_as(_dp)
+        veff = np.ascontiguousarray(cluster.veff, dtype=np.float64)
+        h = _vp()
+        check(lib().sparc_op_create(ctypes.byref(g), veff.ctypes.data_as(_dp), len(cluster.atoms), atoms,
+                                    ctypes.byref(h)), "sparc_op_create")
+        self._keep = []
+        self.handle = h
+        self.nd = int(lib().sparc_op_nd(h))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().sparc_op_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- workspaces
+    def workspace(self, dtype_code: int, ns: int, which: int, device=None):
+        import torch
+        nb = int(lib().sparc_workspace_bytes(self.handle, dtype_code, ns, which))
+        return torch.empty(max(nb, 1), dtype=torch.uint8, device=device or "cuda")
+
+    # -- entry points
+    def h_apply(self, X, Y=None, ws=None, stream=None):
+        import torch
+        ns, ldx = _block(X, self.nd, "X")
+        if Y is None:
+            Y = torch.empty_like(X)
+        _, ldy = _block(Y, self.nd, "Y")
+        dt = _dtype_code(X)
+        if ws is None:
+            ws = self.workspace(dt, ns, 0, X.device)
+        check(lib().sparc_h_apply(self.handle, dt, _ptr(X), ldx, _ptr(Y), ldy, ns, _ptr(ws), ws.numel(),
+                                  _stream(stream)), "sparc_h_apply")
+        return Y
+
+    def cheb_filter(self, X, m: int, a0: float, a: float, b: float, Y=None, ws=None, stream=None):
+        import torch
+        ns, ldx = _block(X, self.nd, "X")
+        if Y is None:
+            Y = torch.empty_like(X)
+        _, ldy = _block(Y, self.nd, "Y")
+        dt = _dtype_code(X)
+        if ws is None:
+            ws = self.workspace(dt, ns, 1, X.device)
+        check(lib().sparc_cheb_filter(self.handle, dt, _ptr(X), ldx, _ptr(Y), ldy, ns, int(m), float(a0),
+                                      float(a), float(b), _ptr(ws), ws.numel(), _stream(stream)),
+              "sparc_cheb_filter")
+        return Y
+
+    def lanczos(self, k: int, v0, stream=None):
+        import torch
+        if v0.dtype != torch.float64 or v0.numel() != self.nd or not v0.is_cuda:
+            raise ValueError("v0 must be a device float64 vector of N_d values")
+        nb = int(lib().sparc_lanczos_workspace_bytes(self.handle, k))
+        ws = torch.empty(nb, dtype=torch.uint8, device=v0.device)
+        alpha = np.zeros(k)
+        beta = np.zeros(max(k - 1, 1))
+        theta = np.zeros(k)
+        check(lib().sparc_lanczos(self.handle, int(k), _ptr(v0), alpha.ctypes.data_as(_dp), beta.ctypes.data_as(_dp),
+                                  theta.ctypes.data_as(_dp), _ptr(ws), nb, _stream(stream)), "sparc_lanczos")
+        return alpha, beta[: k - 1], theta
+
+    def upper_bound(self) -> float:
+        ub = ctypes.c_double()
+        check(lib().sparc_upper_bound(self.handle, ctypes.byref(ub)), "sparc_upper_bound")
+        return ub.value
+
+    def rayleigh_ritz(self, Yf, want_vectors: bool = True, stream=None):
+        import torch
+        ns, ldy = _block(Yf, self.nd, "Y")
+        dt = _dtype_code(Yf)
+        nb = int(lib().sparc_rr_workspace_bytes(self.handle, dt, ns))
+        ws = torch.empty(nb, dtype=torch.uint8, device=Yf.device)
+        theta = np.zeros(ns)
+        evec = torch.empty((ns, ns), dtype=torch.float64, device=Yf.device) if want_vectors else None
+        check(lib().sparc_rayleigh_ritz(self.handle, dt, _ptr(Yf), ldy, ns, theta.ctypes.data_as(_dp),
+                                        _ptr(evec) if evec is not None else None, _ptr(ws), nb, _stream(stream)),
+              "sparc_rayleigh_ritz")
+        # evec is column-major ns x ns: as a torch (ns, ns) row-major tensor it is Q^T
+        return theta, evec
+
+    def step_config(self, dtype_code: int, ns: int):
+        tz, ty, cx = _i32(), _i32(), _i32()
+        check(lib().sparc_step_config(self.handle, dtype_code, ns, ctypes.byref(tz), ctypes.byref(ty),
+                                      ctypes.byref(cx)), "sparc_step_config")
+        return tz.value, ty.value, cx.value
+
+
+def select_bounds(theta, nwant: int = 8, shift: float = 0.1, bfactor: float = 1.01, ubound: float = 0.0):
+    th = np.ascontiguousarray(np.sort(np.asarray(theta, dtype=np.float64)))
+    a0, a, b = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    check(lib().sparc_select_bounds(th.ctypes.data_as(_dp), len(th), int(nwant), float(shift), float(bfactor),
+                                    float(ubound), ctypes.byref(a0), ctypes.byref(a), ctypes.byref(b)),
+          "sparc_select_bounds")
+    return a0.value, a.value, b.value
+
+
+def rotate(Y, Qt, out=None, stream=None):
+    """Psi = Psi_f Q; Y and out are (ns, nd) blocks, Qt the (ns, ns) tensor
+    returned by ``Operator.rayleigh_ritz`` (column-major Q)."""
+    import torch
+    ns, ldy = Y.shape[0], Y.stride(0)
+    nd = Y.shape[1]
+    if out is None:
+        out = torch.empty_like(Y)
+    dt = _dtype_code(Y)
+    ws = torch.empty(ns * ns * 4 if dt == SPARC_F32 else 1, dtype=torch.uint8, device=Y.device)
+    check(lib().sparc_rotate(dt, _ptr(Y), ldy, nd, ns, _ptr(Qt), _ptr(out), out.stride(0), _ptr(ws), ws.numel(),
+                             _stream(stream)), "sparc_rotate")
+    return out
+
+
+class profile:
+    """Per-kernel HIP-event timing inside the library (0 = fused step, 1 = gather)."""
+
+    @staticmethod
+    def enable(on: bool = True):
+        check(lib().sparc_profile_enable(1 if on else 0))
+
+    @staticmethod
+    def reset():
+        check(lib().sparc_profile_reset())
+
+    @staticmethod
+    def read(kernel: int):
+        n = _i64()
+        ms = ctypes.c_double()
+        check(lib().sparc_profile_read(int(kernel), ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
