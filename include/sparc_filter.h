@@ -91,9 +91,9 @@ typedef struct sparc_op sparc_op;
 
 /* Build the discrete Hamiltonian of one cluster on the current HIP device.
  * veff: host array of N_d values of V_eff at the nodes.  The op keeps device
- * copies of V_eff and chi in FP64 and FP32, the per-tile atom lists of the
- * fused kernel, and nothing else; it is immutable afterwards and may be used
- * from several streams at once.  Synchronous.
+ * copies of V_eff and chi in FP64 and FP32 and the index tables of the
+ * projector cubes, and nothing else; it may be used from several streams at
+ * once (sparc_op_set_launch aside).  Synchronous.
  * Errors: SPARC_E_ARG (null pointers, natoms < 0, nproj outside 1..16),
  * SPARC_E_SHAPE (n < 1, h <= 0, radius outside 1..6, cube outside the grid),
  * SPARC_E_NOMEM, SPARC_E_HIP. */
@@ -132,7 +132,7 @@ int sparc_h_apply(const sparc_op *op, int32_t dtype, const void *X, int64_t ldx,
  * a0 plays lambda_1, a the cutoff lambda_c and b lambda_{N_d} of Alg. 2.
  * X (ldx) is read only; Y (ldy) receives the result; neither may overlap the
  * other or ws.  ws: sparc_workspace_bytes(op, dtype, ns, 1) bytes.
- * Asynchronous: 2m kernel launches (m when the op has no atoms).
+ * Asynchronous: 3m kernel launches (m when the op has no atoms).
  * Errors: SPARC_E_BOUNDS (m < 1 or not a0 < a < b), SPARC_E_ARG,
  * SPARC_E_SHAPE, SPARC_E_ALIAS, SPARC_E_WORKSPACE, SPARC_E_HIP. */
 int sparc_cheb_filter(const sparc_op *op, int32_t dtype, const void *X, int64_t ldx, void *Y, int64_t ldy,
@@ -197,13 +197,21 @@ const char *sparc_status_str(int status);
 const char *sparc_last_error(void);
 
 /* Per-kernel timing with HIP events recorded around each launch on the
- * launching stream.  kernel: 0 = fused stencil/recurrence step, 1 = projector
- * gather.  enable(1) starts recording; read() synchronises the recorded
- * events and returns the number of launches and their summed duration in ms;
- * reset() clears the counts. */
+ * launching stream.  kernel: 0 = fused stencil/potential/recurrence step,
+ * 1 = projector gather, 2 = projector scatter.  enable(1) starts recording;
+ * read() synchronises the recorded events and returns the number of launches
+ * and their summed duration in ms; reset() clears the counts. */
 int sparc_profile_enable(int32_t on);
 int sparc_profile_read(int32_t kernel, int64_t *launches, double *total_ms);
 int sparc_profile_reset(void);
+
+/* Override the launch configuration of the fused step kernel for one dtype:
+ * tile extent along z and y (one of 32x32, 64x16, 64x8, 32x16) and the number
+ * of x-planes per workgroup (chunk_x <= 0: library choice).  tile_z = tile_y
+ * = 0 restores the library's tile choice.  Results do not depend on the
+ * configuration.  Not thread-safe against calls that use the op.
+ * Errors: SPARC_E_ARG (null op, bad dtype, unsupported tile). */
+int sparc_op_set_launch(sparc_op *op, int32_t dtype, int32_t tile_z, int32_t tile_y, int32_t chunk_x);
 
 /* Launch configuration of the fused step kernel for a dtype and ns: tile
  * extent along z and y and the x-chunk length, as chosen by the library for

@@ -72,6 +72,7 @@ _SIGS = {
     "sparc_profile_enable": (_i32, [_i32]),
     "sparc_profile_read": (_i32, [_i32, ctypes.POINTER(_i64), _dp]),
     "sparc_profile_reset": (_i32, []),
+    "sparc_op_set_launch": (_i32, [_vp, _i32, _i32, _i32, _i32]),
     "sparc_step_config": (_i32, [_vp, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
 }
 
@@ -253,6 +254,9 @@ class Operator:
         # evec is column-major ns x ns: as a torch (ns, ns) row-major tensor it is Q^T
         return theta, evec
 
+    def set_launch(self, dtype_code: int, tile_z: int = 0, tile_y: int = 0, chunk_x: int = 0):
+        check(lib().sparc_op_set_launch(self.handle, dtype_code, tile_z, tile_y, chunk_x), "sparc_op_set_launch")
+
     def step_config(self, dtype_code: int, ns: int):
         tz, ty, cx = _i32(), _i32(), _i32()
         check(lib().sparc_step_config(self.handle, dtype_code, ns, ctypes.byref(tz), ctypes.byref(ty),
@@ -285,7 +289,7 @@ def rotate(Y, Qt, out=None, stream=None):
 
 
 class profile:
-    """Per-kernel HIP-event timing inside the library (0 = fused step, 1 = gather)."""
+    """Per-kernel HIP-event timing inside the library (0 = fused step, 1 = gather, 2 = scatter)."""
 
     @staticmethod
     def enable(on: bool = True):

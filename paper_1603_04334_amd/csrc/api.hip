@@ -31,8 +31,8 @@ struct ProfRec {
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRec> g_prof_pending;
-int64_t g_prof_count[2] = {0, 0};
-double g_prof_ms[2] = {0, 0};
+int64_t g_prof_count[3] = {0, 0, 0};
+double g_prof_ms[3] = {0, 0, 0};
 }  // namespace
 
 ProfScope::ProfScope(int k, hipStream_t s) : kernel(k), stream(s)
@@ -98,6 +98,16 @@ static int check_block(const sparc_op *op, const void *p, int64_t ld, int ns, co
     return SPARC_OK;
 }
 
+int launch_h_step(const sparc_op *op, int dtype, const void *yk, int64_t ldk, const void *yprev, int64_t ldp,
+                  void *out, int64_t ldo, int ns, void *part, const StepCoef &c, const StepLaunch &L,
+                  hipStream_t stream)
+{
+    int st;
+    if ((st = launch_gather(op, dtype, yk, ldk, ns, part, stream))) return st;
+    if ((st = launch_step(op, dtype, yk, ldk, yprev, ldp, out, ldo, ns, c, L, stream))) return st;
+    return launch_scatter(op, dtype, out, ldo, ns, part, c.alpha, stream);
+}
+
 }  // namespace sparc
 
 using namespace sparc;
@@ -142,14 +152,16 @@ int sparc_profile_reset(void)
         (void)hipEventDestroy(r.b);
     }
     g_prof_pending.clear();
-    g_prof_count[0] = g_prof_count[1] = 0;
-    g_prof_ms[0] = g_prof_ms[1] = 0;
+    for (int k = 0; k < 3; ++k) {
+        g_prof_count[k] = 0;
+        g_prof_ms[k] = 0;
+    }
     return SPARC_OK;
 }
 
 int sparc_profile_read(int32_t kernel, int64_t *launches, double *total_ms)
 {
-    if (kernel < 0 || kernel > 1) return fail(SPARC_E_ARG, "kernel id must be 0 or 1");
+    if (kernel < 0 || kernel > 2) return fail(SPARC_E_ARG, "kernel id must be 0, 1 or 2");
     std::lock_guard<std::mutex> lk(g_prof_mu);
     for (auto &r : g_prof_pending) {
         if (hipEventSynchronize(r.b) != hipSuccess) return fail(SPARC_E_HIP, "event synchronisation failed");
@@ -208,7 +220,7 @@ int sparc_op_create(const sparc_grid *grid, const double *veff, int32_t natoms, 
 
     // atoms
     op->natoms = natoms;
-    int64_t chi_total = 0;
+    int64_t chi_total = 0, box_total = 0;
     for (int J = 0; J < natoms; ++J) {
         const sparc_atom &A = atoms[J];
         if (A.nproj < 1 || A.nproj > kMaxProj || !A.chi || !A.gamma)
@@ -225,6 +237,8 @@ int sparc_op_create(const sparc_grid *grid, const double *veff, int32_t natoms, 
         a.proj0 = op->nproj_total;
         a.chi0 = chi_total;
         const int64_t nbox = (int64_t)A.ext[0] * A.ext[1] * A.ext[2];
+        a.box0 = (int)box_total;
+        box_total += nbox;
         chi_total += nbox * A.nproj;
         op->nproj_total += A.nproj;
         op->max_nproj = std::max(op->max_nproj, A.nproj);
@@ -268,32 +282,83 @@ int sparc_op_create(const sparc_grid *grid, const double *veff, int32_t natoms, 
             return cleanup(fail(SPARC_E_HIP, "copy of projector data failed"));
     }
 
-    // per-tile atom lists for every tile shape of the fused kernel
-    for (int s = 0; s < kNumShapes; ++s) {
-        TileLists &tl = op->lists[s];
-        const int TY = kShapes[s].ty(), TZ = kShapes[s].tz;
-        tl.tiles_y = (op->n[1] + TY - 1) / TY;
-        tl.tiles_z = (op->n[2] + TZ - 1) / TZ;
-        const int ntiles = tl.tiles_y * tl.tiles_z;
-        std::vector<int> off(ntiles + 1, 0), list;
-        for (int ty = 0; ty < tl.tiles_y; ++ty)
-            for (int tz = 0; tz < tl.tiles_z; ++tz) {
-                const int y0 = ty * TY, y1 = std::min(op->n[1], y0 + TY);
-                const int z0 = tz * TZ, z1 = std::min(op->n[2], z0 + TZ);
-                for (int J = 0; J < natoms; ++J) {
-                    const AtomDev &a = op->atoms[J];
-                    if (a.lo[1] < y1 && a.lo[1] + a.ext[1] > y0 && a.lo[2] < z1 && a.lo[2] + a.ext[2] > z0)
-                        list.push_back(J);
-                }
-                off[ty * tl.tiles_z + tz + 1] = (int)list.size();
+    // cube-point grid offsets and the unique covered nodes with their (atom, cube index) entries
+    if (natoms > 0) {
+        if (box_total > 0x7fffffffLL) return cleanup(fail(SPARC_E_SHAPE, "projector cubes too large"));
+        std::vector<int> boff(box_total);
+        std::vector<std::pair<int64_t, std::pair<int, int>>> cover;
+        cover.reserve(box_total);
+        for (int J = 0; J < natoms; ++J) {
+            const AtomDev &a = op->atoms[J];
+            int loc = 0;
+            for (int i = 0; i < a.ext[0]; ++i)
+                for (int j = 0; j < a.ext[1]; ++j)
+                    for (int k = 0; k < a.ext[2]; ++k, ++loc) {
+                        const int64_t g = (int64_t)(a.lo[2] + k) + (int64_t)op->n[2] * ((a.lo[1] + j) + (int64_t)op->n[1] * (a.lo[0] + i));
+                        boff[a.box0 + loc] = (int)g;
+                        cover.push_back({g, {J, loc}});
+                    }
+        }
+        std::stable_sort(cover.begin(), cover.end(),
+                         [](const auto &x, const auto &y) { return x.first < y.first; });
+        // unique nodes and their (atom, cube index) entries
+        std::vector<int> pts, off;
+        std::vector<std::pair<int, int>> raw;
+        for (size_t e = 0; e < cover.size(); ++e) {
+            if (e == 0 || cover[e].first != cover[e - 1].first) {
+                pts.push_back((int)cover[e].first);
+                off.push_back((int)e);
             }
-        if (hipMalloc(&tl.d_off, off.size() * sizeof(int)) != hipSuccess ||
-            hipMalloc(&tl.d_list, std::max<size_t>(1, list.size()) * sizeof(int)) != hipSuccess)
-            return cleanup(fail(SPARC_E_NOMEM, "device allocation of tile lists failed"));
-        if (hipMemcpy(tl.d_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
-            (!list.empty() &&
-             hipMemcpy(tl.d_list, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess))
-            return cleanup(fail(SPARC_E_HIP, "copy of tile lists failed"));
+            raw.push_back(cover[e].second);
+        }
+        off.push_back((int)cover.size());
+        // scatter blocks: at most kBlock nodes touching at most kScatterSlots atoms
+        std::vector<int> blk_pt{0}, blk_at{0}, blk_atoms, ent(4 * raw.size());
+        std::vector<int> slot_of(natoms, -1);
+        std::vector<int> cur;
+        auto close_block = [&](int end_pt) {
+            blk_pt.push_back(end_pt);
+            for (int J : cur) {
+                blk_atoms.push_back(J);
+                slot_of[J] = -1;
+            }
+            blk_at.push_back((int)blk_atoms.size());
+            cur.clear();
+        };
+        for (size_t pi = 0; pi < pts.size(); ++pi)
+            if (off[pi + 1] - off[pi] > kScatterSlots)
+                return cleanup(fail(SPARC_E_SHAPE, "more than 32 projector cubes overlap at one node"));
+        for (size_t pi = 0; pi < pts.size(); ++pi) {
+            int fresh = 0;
+            for (int e = off[pi]; e < off[pi + 1]; ++e)
+                if (slot_of[raw[e].first] < 0) ++fresh;
+            const int in_block = (int)pi - blk_pt.back();
+            if (in_block == kBlock || (int)cur.size() + fresh > kScatterSlots) close_block((int)pi);
+            for (int e = off[pi]; e < off[pi + 1]; ++e) {
+                const int J = raw[e].first;
+                if (slot_of[J] < 0) {
+                    slot_of[J] = (int)cur.size();
+                    cur.push_back(J);
+                }
+                const AtomDev &a = op->atoms[J];
+                const int nbox = a.ext[0] * a.ext[1] * a.ext[2];
+                ent[4 * e + 0] = (int)(a.chi0 + raw[e].second);
+                ent[4 * e + 1] = nbox;
+                ent[4 * e + 2] = slot_of[J];
+                ent[4 * e + 3] = a.nproj;
+            }
+        }
+        close_block((int)pts.size());
+        if (chi_total > 0x7fffffffLL) return cleanup(fail(SPARC_E_SHAPE, "projector data too large"));
+        op->nl_npts = (int)pts.size();
+        op->nl_nblk = (int)blk_pt.size() - 1;
+        auto up = [&](int **dst, const std::vector<int> &v) {
+            if (hipMalloc(dst, std::max<size_t>(1, v.size()) * sizeof(int)) != hipSuccess) return false;
+            return v.empty() || hipMemcpy(*dst, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+        };
+        if (!up(&op->d_box_off, boff) || !up(&op->d_nl_pts, pts) || !up(&op->d_nl_off, off) || !up(&op->d_nl_ent, ent) ||
+            !up(&op->d_nl_blk_pt, blk_pt) || !up(&op->d_nl_blk_at, blk_at) || !up(&op->d_nl_blk_atoms, blk_atoms))
+            return cleanup(fail(SPARC_E_NOMEM, "device allocation of projector tables failed"));
     }
     *out = op;
     return SPARC_OK;
@@ -309,10 +374,13 @@ int sparc_op_destroy(sparc_op *op)
     (void)hipFree(op->d_chi32);
     (void)hipFree(op->d_hg64);
     (void)hipFree(op->d_hg32);
-    for (auto &tl : op->lists) {
-        (void)hipFree(tl.d_off);
-        (void)hipFree(tl.d_list);
-    }
+    (void)hipFree(op->d_box_off);
+    (void)hipFree(op->d_nl_pts);
+    (void)hipFree(op->d_nl_off);
+    (void)hipFree(op->d_nl_ent);
+    (void)hipFree(op->d_nl_blk_pt);
+    (void)hipFree(op->d_nl_blk_at);
+    (void)hipFree(op->d_nl_blk_atoms);
     delete op;
     return SPARC_OK;
 }
@@ -323,10 +391,25 @@ int32_t sparc_op_nproj(const sparc_op *op) { return op ? op->nproj_total : 0; }
 size_t sparc_workspace_bytes(const sparc_op *op, int32_t dtype, int32_t ns, int32_t which)
 {
     if (!op || ns < 1 || (dtype != SPARC_F64 && dtype != SPARC_F32)) return 0;
-    const size_t es = elem_size(dtype);
-    size_t g = align_up((size_t)op->nproj_total * ns * es);
+    const size_t g = gather_bytes(op, dtype, ns);
     if (which == 0) return g;
-    return g + align_up((size_t)op->nd * ns * es);
+    return g + align_up((size_t)op->nd * ns * elem_size(dtype));
+}
+
+int sparc_op_set_launch(sparc_op *op, int32_t dtype, int32_t tile_z, int32_t tile_y, int32_t chunk_x)
+{
+    if (!op || (dtype != SPARC_F64 && dtype != SPARC_F32)) return fail(SPARC_E_ARG, "null op or bad dtype");
+    if (tile_z <= 0 && tile_y <= 0) {
+        op->tune_shape[dtype] = -1;
+    } else {
+        int found = -1;
+        for (int s = 0; s < kNumShapes; ++s)
+            if (kShapes[s].tz == tile_z && kShapes[s].ty() == tile_y) found = s;
+        if (found < 0) return fail(SPARC_E_ARG, "unsupported tile shape");
+        op->tune_shape[dtype] = found;
+    }
+    op->tune_chunk[dtype] = chunk_x > 0 ? chunk_x : 0;
+    return SPARC_OK;
 }
 
 int sparc_step_config(const sparc_op *op, int32_t dtype, int32_t ns, int32_t *tile_z, int32_t *tile_y,
@@ -354,9 +437,8 @@ int sparc_h_apply(const sparc_op *op, int32_t dtype, const void *X, int64_t ldx,
         return fail(SPARC_E_ALIAS, "X, Y and the workspace must not overlap");
     hipStream_t s = (hipStream_t)stream;
     StepLaunch L = choose_step_launch(op, dtype, ns);
-    if ((st = launch_gather(op, dtype, X, ldx, ns, ws, s))) return st;
     StepCoef c{1.0, 0.0, 0.0, 0};
-    return launch_step(op, dtype, X, ldx, nullptr, 0, Y, ldy, ns, ws, c, L, s);
+    return launch_h_step(op, dtype, X, ldx, nullptr, 0, Y, ldy, ns, ws, c, L, s);
 }
 
 int sparc_cheb_filter(const sparc_op *op, int32_t dtype, const void *X, int64_t ldx, void *Y, int64_t ldy,
@@ -376,9 +458,8 @@ int sparc_cheb_filter(const sparc_op *op, int32_t dtype, const void *X, int64_t 
         return fail(SPARC_E_ALIAS, "X, Y and the workspace must not overlap");
 
     hipStream_t s = (hipStream_t)stream;
-    const size_t es = elem_size(dtype);
     char *G = (char *)ws;
-    char *W = G + align_up((size_t)op->nproj_total * ns * es);
+    char *W = G + gather_bytes(op, dtype, ns);
     const int64_t ldw = op->nd;
 
     // Y_k is written to buffer P for odd k and Q for even k, so that Y_m
@@ -395,9 +476,8 @@ int sparc_cheb_filter(const sparc_op *op, int32_t dtype, const void *X, int64_t 
     StepLaunch L = choose_step_launch(op, dtype, ns);
 
     // Y_1 = (sigma_1/e)(H - cI) X
-    if ((st = launch_gather(op, dtype, X, ldx, ns, G, s))) return st;
     StepCoef c1{sigma1 / e, 0.0, c, 0};
-    if ((st = launch_step(op, dtype, X, ldx, nullptr, 0, P, ldP, ns, G, c1, L, s))) return st;
+    if ((st = launch_h_step(op, dtype, X, ldx, nullptr, 0, P, ldP, ns, G, c1, L, s))) return st;
 
     double sigma = sigma1;
     for (int k = 1; k < m; ++k) {
@@ -408,9 +488,8 @@ int sparc_cheb_filter(const sparc_op *op, int32_t dtype, const void *X, int64_t 
         const int64_t ldp = (k == 1) ? ldx : ((k & 1) ? ldQ : ldP);
         void *out = ((k + 1) & 1) ? P : Q;
         const int64_t ldo = ((k + 1) & 1) ? ldP : ldQ;
-        if ((st = launch_gather(op, dtype, yk, ldk, ns, G, s))) return st;
         StepCoef ck{2.0 * sigma_next / e, sigma * sigma_next, c, 1};
-        if ((st = launch_step(op, dtype, yk, ldk, yprev, ldp, out, ldo, ns, G, ck, L, s))) return st;
+        if ((st = launch_h_step(op, dtype, yk, ldk, yprev, ldp, out, ldo, ns, G, ck, L, s))) return st;
         sigma = sigma_next;
     }
     return SPARC_OK;

@@ -15,6 +15,8 @@ namespace sparc {
 constexpr int kMaxRadius = 6;    // largest stencil half-width n_o supported
 constexpr int kMaxProj = 16;     // largest projector count per atom
 constexpr int kBlock = 256;      // threads per workgroup of the stencil kernels
+constexpr int kGatherSplit = 4;  // workgroups sharing one atom's cube points in the gather
+constexpr int kScatterSlots = 32;  // most atoms one scatter block may touch
 
 // Per-atom record used by the device kernels.
 struct AtomDev {
@@ -22,6 +24,7 @@ struct AtomDev {
     int ext[3];
     int nproj;
     int proj0;        // index of the atom's first projector in the global projector list
+    int box0;         // offset of the atom's cube in the cube-point offset table
     long long chi0;   // offset of the atom's chi block (nproj * nbox values)
 };
 
@@ -34,12 +37,6 @@ struct TileShape {
 };
 constexpr int kNumShapes = 4;
 extern const TileShape kShapes[kNumShapes];
-
-struct TileLists {
-    int tiles_y = 0, tiles_z = 0;
-    int *d_off = nullptr;   // tiles_y*tiles_z + 1 offsets into d_list
-    int *d_list = nullptr;  // atom indices whose cube meets the tile's (y,z) footprint
-};
 
 }  // namespace sparc
 
@@ -65,7 +62,21 @@ struct sparc_op {
     float *d_chi32 = nullptr;
     double *d_hg64 = nullptr;  // h^3 gamma per global projector
     float *d_hg32 = nullptr;
-    sparc::TileLists lists[sparc::kNumShapes];
+    int *d_box_off = nullptr;  // grid index of every cube point (atoms back to back)
+    // unique nodes covered by at least one projector cube, their entries
+    // (chi index of projector 0, cube size, block slot, nproj) and the
+    // scatter blocks (node ranges and the atoms each touches)
+    int nl_npts = 0;
+    int nl_nblk = 0;
+    int *d_nl_pts = nullptr;
+    int *d_nl_off = nullptr;
+    int *d_nl_ent = nullptr;  // int4 records
+    int *d_nl_blk_pt = nullptr;
+    int *d_nl_blk_at = nullptr;
+    int *d_nl_blk_atoms = nullptr;
+    // launch overrides (set by sparc_op_set_launch; -1 / 0 = library choice)
+    int tune_shape[2] = {-1, -1};
+    int tune_chunk[2] = {0, 0};
 };
 
 namespace sparc {
@@ -97,14 +108,29 @@ struct StepLaunch {
 
 StepLaunch choose_step_launch(const sparc_op *op, int dtype, int ns);
 
-// enqueue the projector gather G[p][c] = h^3 gamma_p sum_x chi_p(x) Y(x,c)
-int launch_gather(const sparc_op *op, int dtype, const void *Y, int64_t ldy, int ns, void *G,
+// bytes of the gather's partial projections for ns columns
+inline size_t gather_bytes(const sparc_op *op, int dtype, int ns)
+{
+    return align_up((size_t)kGatherSplit * (op->nproj_total > 0 ? op->nproj_total : 1) * ns *
+                    (dtype == SPARC_F64 ? 8 : 4));
+}
+
+// enqueue the projector gather: split partial sums of chi_Jp^T Y(:,c) per atom
+int launch_gather(const sparc_op *op, int dtype, const void *Y, int64_t ldy, int ns, void *part,
                   hipStream_t stream);
 
-// enqueue one fused step
+// enqueue the projector scatter: out += alpha * V_nl Y from the gathered partials
+int launch_scatter(const sparc_op *op, int dtype, void *out, int64_t ldo, int ns, const void *part, double alpha,
+                   hipStream_t stream);
+
+// enqueue one fused stencil / potential / recurrence step (local part of H)
 int launch_step(const sparc_op *op, int dtype, const void *yk, int64_t ldk, const void *yprev, int64_t ldp,
-                void *out, int64_t ldo, int ns, const void *G, const StepCoef &c, const StepLaunch &L,
-                hipStream_t stream);
+                void *out, int64_t ldo, int ns, const StepCoef &c, const StepLaunch &L, hipStream_t stream);
+
+// the full operator step: gather(yk), local step, scatter(alpha)
+int launch_h_step(const sparc_op *op, int dtype, const void *yk, int64_t ldk, const void *yprev, int64_t ldp,
+                  void *out, int64_t ldo, int ns, void *part, const StepCoef &c, const StepLaunch &L,
+                  hipStream_t stream);
 
 // profiling hooks (no-ops unless enabled)
 struct ProfScope {

@@ -23,60 +23,93 @@
 
 namespace sparc {
 
-constexpr int kRedBlocks = 512;  // blocks of the first reduction pass
+constexpr int kRedBlocks = 1024;          // blocks of the first reduction pass
+constexpr int kRedWaves = kRedBlocks * 4;  // one partial per wave
+constexpr int kDotGroup = 8;              // vectors per pass over a wave's segment
 
-// partial[b*nv + i] = sum over block b's points of V_i(x) * w(x)
+__device__ inline double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// wave-level partial inner products: partial[gw*(nv+1) + i] = sum over wave
+// gw's points of V_i(x) w(x) for i < nv, and of w(x)^2 for i = nv.  Each wave
+// owns a contiguous segment of the vectors; groups of 8 vectors per pass.
 __global__ void __launch_bounds__(256) multidot_kernel(const double *__restrict__ V, long long ldv, int nv,
                                                        const double *__restrict__ w, long long n,
                                                        double *__restrict__ partial)
 {
+    const int lane = threadIdx.x & 63;
+    const long long gw = blockIdx.x * 4LL + (threadIdx.x >> 6);
+    const long long nw = gridDim.x * 4LL;
+    const long long seg = ((n + nw - 1) / nw + 63) / 64 * 64;
+    const long long beg = gw * seg;
+    const long long end = (beg + seg < n) ? beg + seg : n;
+    double *out = partial + gw * (nv + 1);
+    for (int i0 = 0; i0 <= nv; i0 += kDotGroup) {
+        double acc[kDotGroup];
+#pragma unroll
+        for (int u = 0; u < kDotGroup; ++u) acc[u] = 0.0;
+        for (long long x = beg + lane; x < end; x += 64) {
+            const double wx = w[x];
+#pragma unroll
+            for (int u = 0; u < kDotGroup; ++u) {
+                const int i = i0 + u;
+                const double vx = (i < nv) ? V[(long long)i * ldv + x] : wx;
+                acc[u] += (i <= nv) ? vx * wx : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kDotGroup; ++u) {
+            const double t = wave_sum(acc[u]);
+            if (lane == 0 && i0 + u <= nv) out[i0 + u] = t;
+        }
+    }
+}
+
+// out[i] = sum over the kRedWaves wave partials of entry i (stride per wave),
+// one block per i, fixed tree order.  alpha_out[0] = out[alpha_index] if set;
+// mode 1 stores the square root.
+__global__ void __launch_bounds__(256) finish_sums(const double *partial, int stride, double *out,
+                                                   double *alpha_out, int alpha_index, int mode)
+{
     __shared__ double red[4];
-    const long long chunk = (n + gridDim.x - 1) / gridDim.x;
-    const long long beg = blockIdx.x * chunk;
-    const long long end = (beg + chunk < n) ? beg + chunk : n;
-    for (int i = 0; i < nv; ++i) {
-        const double *v = V + (long long)i * ldv;
-        double s = 0.0;
-        for (long long x = beg + threadIdx.x; x < end; x += blockDim.x) s += v[x] * w[x];
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) partial[(long long)blockIdx.x * nv + i] = (red[0] + red[1]) + (red[2] + red[3]);
-        __syncthreads();
+    const int i = blockIdx.x;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < kRedWaves; b += 256) v += partial[(long long)b * stride + i];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double t = (red[0] + red[1]) + (red[2] + red[3]);
+        out[i] = mode == 1 ? sqrt(t) : t;
+        if (alpha_out && i == alpha_index) alpha_out[0] = t;
     }
 }
 
-// out[i] = sum_b partial[b*nv + i] (fixed order); mode 1 stores sqrt of the sum
-__global__ void multidot_finish(const double *partial, int nblocks, int nv, double *out, int mode)
+// w -= sum_i coeff[i] V_i, and partial[gw] = sum over wave gw's points of the new w^2
+__global__ void __launch_bounds__(256) orth_apply_norm(double *w, const double *__restrict__ V, long long ldv, int nv,
+                                                       const double *__restrict__ coeff, long long n,
+                                                       double *__restrict__ partial)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nv) return;
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += partial[(long long)b * nv + i];
-    out[i] = mode == 1 ? sqrt(s) : s;
-}
-
-// w -= alpha_j v_j + beta_{j-1} v_{j-1}
-__global__ void lanczos_update(double *w, const double *vj, const double *vjm1, const double *alpha_j,
-                               const double *beta_jm1, long long n)
-{
-    const double al = *alpha_j;
-    const double be = beta_jm1 ? *beta_jm1 : 0.0;
-    for (long long x = blockIdx.x * (long long)blockDim.x + threadIdx.x; x < n; x += (long long)gridDim.x * blockDim.x) {
-        double r = w[x] - al * vj[x];
-        if (vjm1) r -= be * vjm1[x];
-        w[x] = r;
-    }
-}
-
-// w -= sum_i coeff[i] V_i
-__global__ void reorth_apply(double *w, const double *V, long long ldv, int nv, const double *coeff, long long n)
-{
-    for (long long x = blockIdx.x * (long long)blockDim.x + threadIdx.x; x < n; x += (long long)gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & 63;
+    const long long gw = blockIdx.x * 4LL + (threadIdx.x >> 6);
+    const long long nw = gridDim.x * 4LL;
+    const long long seg = ((n + nw - 1) / nw + 63) / 64 * 64;
+    const long long beg = gw * seg;
+    const long long end = (beg + seg < n) ? beg + seg : n;
+    double nrm = 0.0;
+    for (long long x = beg + lane; x < end; x += 64) {
         double s = 0.0;
+#pragma unroll 8
         for (int i = 0; i < nv; ++i) s += coeff[i] * V[(long long)i * ldv + x];
-        w[x] -= s;
+        const double r = w[x] - s;
+        w[x] = r;
+        nrm += r * r;
     }
+    nrm = wave_sum(nrm);
+    if (lane == 0) partial[gw] = nrm;
 }
 
 // dst = src / *norm
@@ -100,6 +133,123 @@ __global__ void f64_to_f32_dense(const double *src, float *dst, long long n)
 {
     for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x)
         dst[t] = (float)src[t];
+}
+
+// ---------------------------------------------------------------- Rayleigh-Ritz projection
+//
+// M_s = Y^T Y and H_s = Y^T (HY) in FP64 on the matrix cores
+// (v_mfma_f64_16x16x4f64).  The contraction runs over the N_d grid points,
+// which are split into chunks; a workgroup owns one 64 x 64 tile pair of
+// (M_s, H_s) for one chunk, stages 32-point slices of the three column
+// panels in LDS (coalesced along the contiguous grid axis) and writes its
+// partial tiles, which a second kernel sums in chunk order.  Each of the four
+// waves owns a 32 x 32 quarter of both tiles (2 x 2 MFMA blocks each).
+
+constexpr int kRrTile = 64;
+constexpr int kRrK = 32;
+
+__device__ inline void mfma_f64(double a, double b, double (&acc)[4])
+{
+    typedef double v4d __attribute__((ext_vector_type(4)));
+    v4d c = {acc[0], acc[1], acc[2], acc[3]};
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    acc[0] = c[0];
+    acc[1] = c[1];
+    acc[2] = c[2];
+    acc[3] = c[3];
+}
+
+__global__ void __launch_bounds__(256) rr_project_kernel(const double *__restrict__ Y, long long ldy,
+                                                          const double *__restrict__ HY, long long ldh, long long nd,
+                                                          int ns, long long kchunk, double *__restrict__ partial)
+{
+    __shared__ double sA[kRrTile][kRrK + 1];  // Y columns of the row tile, [col][k]
+    __shared__ double sB[kRrTile][kRrK + 1];  // Y columns of the column tile
+    __shared__ double sH[kRrTile][kRrK + 1];  // HY columns of the column tile
+    const int ti = blockIdx.y, tj = blockIdx.z;
+    const long long k0 = blockIdx.x * kchunk;
+    const long long k1 = (k0 + kchunk < nd) ? k0 + kchunk : nd;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;  // wave's quarter
+    const int li = lane & 15, lk = lane >> 4;
+    const int kk = tid & 31;
+    double accM[2][2][4] = {}, accH[2][2][4] = {};
+    double ra[8], rb[8], rh[8];
+
+    // thread -> (column c = 8*pass + tid/32, point kk = tid%32 of the slice)
+    auto fetch = [&](long long kb) {
+        const long long k = kb + kk;
+        const bool kin = k < k1;
+#pragma unroll
+        for (int pass = 0; pass < 8; ++pass) {
+            const int c = pass * 8 + (tid >> 5);
+            const int ca = ti * kRrTile + c, cb = tj * kRrTile + c;
+            ra[pass] = (kin && ca < ns) ? Y[(long long)ca * ldy + k] : 0.0;
+            rb[pass] = (kin && cb < ns) ? Y[(long long)cb * ldy + k] : 0.0;
+            rh[pass] = (kin && cb < ns) ? HY[(long long)cb * ldh + k] : 0.0;
+        }
+    };
+    fetch(k0);
+    for (long long kb = k0; kb < k1; kb += kRrK) {
+        __syncthreads();
+#pragma unroll
+        for (int pass = 0; pass < 8; ++pass) {
+            const int c = pass * 8 + (tid >> 5);
+            sA[c][kk] = ra[pass];
+            sB[c][kk] = rb[pass];
+            sH[c][kk] = rh[pass];
+        }
+        __syncthreads();
+        if (kb + kRrK < k1) fetch(kb + kRrK);
+#pragma unroll
+        for (int ks = 0; ks < kRrK; ks += 4) {
+            double a[2], b[2], h[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                a[u] = sA[wi + 16 * u + li][ks + lk];
+                b[u] = sB[wj + 16 * u + li][ks + lk];
+                h[u] = sH[wj + 16 * u + li][ks + lk];
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 2; ++v) {
+                    mfma_f64(a[u], b[v], accM[u][v]);
+                    mfma_f64(a[u], h[v], accH[u][v]);
+                }
+        }
+    }
+    // partial[(chunk*2 + which)][col][row] of the full ns x ns matrices
+    const long long mat = (long long)ns * ns;
+    double *pm = partial + (long long)blockIdx.x * 2 * mat;
+    double *ph = pm + mat;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = ti * kRrTile + wi + 16 * u + (lane >> 4) + 4 * r;
+                const int col = tj * kRrTile + wj + 16 * v + (lane & 15);
+                if (row < ns && col < ns) {
+                    pm[(long long)col * ns + row] = accM[u][v][r];
+                    ph[(long long)col * ns + row] = accH[u][v][r];
+                }
+            }
+}
+
+// Ms, Hs (column-major ns x ns) = sum over chunks of the partial tiles, in chunk order
+__global__ void rr_reduce_kernel(const double *partial, int nchunks, int ns, double *Ms, double *Hs)
+{
+    const long long mat = (long long)ns * ns;
+    const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (e >= 2 * mat) return;
+    const long long which = e / mat, off = e - which * mat;
+    double s = 0.0;
+#pragma unroll 16
+    for (int c = 0; c < nchunks; ++c) s += partial[((long long)c * 2 + which) * mat + off];
+    (which == 0 ? Ms : Hs)[off] = s;
 }
 
 // symmetrise an ns x ns matrix in place: A = (A + A^T)/2
@@ -191,12 +341,18 @@ size_t sparc_lanczos_workspace_bytes(const sparc_op *op, int32_t k)
 {
     if (!op || k < 1) return 0;
     size_t b = align_up((size_t)op->nd * (k + 1) * sizeof(double));  // basis V_0..V_{k-1} and w
-    b += align_up((size_t)std::max(1, op->nproj_total) * sizeof(double));  // gathered coefficients
-    b += align_up((size_t)(3 * k + 4) * sizeof(double));                  // alpha, beta, coeff, norm
-    b += align_up((size_t)kRedBlocks * (k + 1) * sizeof(double));         // partial sums
+    b += gather_bytes(op, SPARC_F64, 1);                                  // gathered projections
+    b += align_up((size_t)(4 * k + 8) * sizeof(double));                  // alpha, beta, coeff, norm
+    b += align_up((size_t)kRedWaves * (k + 2) * sizeof(double));          // partial sums
     return b;
 }
 
+// Lanczos with full re-orthogonalisation, one classical Gram-Schmidt pass per
+// step against the whole basis: w = H v_j, c = [v_0..v_j]^T w,
+// w -= [v_0..v_j] c, beta_j = |w|, v_{j+1} = w / beta_j, and alpha_j = c_j.
+// In exact arithmetic c_i = 0 for i < j-1 and c_{j-1} = beta_{j-1}, so this is
+// the three-term Lanczos recurrence with the rounding-induced components along
+// older vectors removed at every step.
 int sparc_lanczos(const sparc_op *op, int32_t k, const double *v0, double *alpha, double *beta, double *theta,
                   void *ws, size_t ws_bytes, void *stream)
 {
@@ -210,41 +366,33 @@ int sparc_lanczos(const sparc_op *op, int32_t k, const double *v0, double *alpha
     double *V = (double *)p;  // k+1 vectors of n (the last is w)
     p += align_up((size_t)n * (k + 1) * sizeof(double));
     double *G = (double *)p;
-    p += align_up((size_t)std::max(1, op->nproj_total) * sizeof(double));
+    p += gather_bytes(op, SPARC_F64, 1);
     double *d_alpha = (double *)p;
     double *d_beta = d_alpha + k;
-    double *d_coeff = d_beta + k;
-    double *d_norm = d_coeff + k;
-    p += align_up((size_t)(3 * k + 4) * sizeof(double));
+    double *d_coeff = d_beta + k;       // k + 1 entries (coefficients and |w|^2)
+    double *d_norm = d_coeff + k + 2;
+    p += align_up((size_t)(4 * k + 8) * sizeof(double));
     double *partial = (double *)p;
     double *w = V + (long long)k * n;
 
     const dim3 sg = stream_grid(n);
-    auto dots = [&](const double *Vb, int nv, const double *vec, double *outv, int mode) -> int {
-        hipLaunchKernelGGL(multidot_kernel, dim3(kRedBlocks), dim3(256), 0, s, Vb, (long long)n, nv, vec, n, partial);
-        hipLaunchKernelGGL(multidot_finish, dim3((nv + 63) / 64), dim3(64), 0, s, partial, kRedBlocks, nv, outv, mode);
-        SPARC_HIP(hipGetLastError());
-        return SPARC_OK;
-    };
     int st;
     // V_0 = v0 / |v0|
-    if ((st = dots(v0, 1, v0, d_norm, 1))) return st;
+    hipLaunchKernelGGL(multidot_kernel, dim3(kRedBlocks), dim3(256), 0, s, v0, (long long)n, 0, v0, n, partial);
+    hipLaunchKernelGGL(finish_sums, dim3(1), dim3(256), 0, s, partial, 1, d_norm, nullptr, -1, 1);
     hipLaunchKernelGGL(scale_by_inverse, sg, dim3(256), 0, s, V, v0, d_norm, n);
     StepLaunch L = choose_step_launch(op, SPARC_F64, 1);
     StepCoef hc{1.0, 0.0, 0.0, 0};
     for (int j = 0; j < k; ++j) {
         double *vj = V + (long long)j * n;
-        if ((st = launch_gather(op, SPARC_F64, vj, n, 1, G, s))) return st;
-        if ((st = launch_step(op, SPARC_F64, vj, n, nullptr, 0, w, n, 1, G, hc, L, s))) return st;
-        if ((st = dots(vj, 1, w, d_alpha + j, 0))) return st;
-        hipLaunchKernelGGL(lanczos_update, sg, dim3(256), 0, s, w, vj, j > 0 ? vj - n : nullptr, d_alpha + j,
-                           j > 0 ? d_beta + (j - 1) : nullptr, n);
-        for (int pass = 0; pass < 2; ++pass) {
-            if ((st = dots(V, j + 1, w, d_coeff, 0))) return st;
-            hipLaunchKernelGGL(reorth_apply, sg, dim3(256), 0, s, w, V, (long long)n, j + 1, d_coeff, n);
-        }
+        if ((st = launch_h_step(op, SPARC_F64, vj, n, nullptr, 0, w, n, 1, G, hc, L, s))) return st;
+        const int nv = j + 1;
+        hipLaunchKernelGGL(multidot_kernel, dim3(kRedBlocks), dim3(256), 0, s, V, (long long)n, nv, w, n, partial);
+        hipLaunchKernelGGL(finish_sums, dim3(nv + 1), dim3(256), 0, s, partial, nv + 1, d_coeff, d_alpha + j, j, 0);
         if (j + 1 < k) {
-            if ((st = dots(w, 1, w, d_beta + j, 1))) return st;
+            hipLaunchKernelGGL(orth_apply_norm, dim3(kRedBlocks), dim3(256), 0, s, w, V, (long long)n, nv, d_coeff, n,
+                               partial);
+            hipLaunchKernelGGL(finish_sums, dim3(1), dim3(256), 0, s, partial, 1, d_beta + j, nullptr, -1, 1);
             hipLaunchKernelGGL(scale_by_inverse, sg, dim3(256), 0, s, vj + n, w, d_beta + j, n);
         }
         SPARC_HIP(hipGetLastError());
@@ -263,15 +411,27 @@ int sparc_lanczos(const sparc_op *op, int32_t k, const double *v0, double *alpha
     return SPARC_OK;
 }
 
+static long long rr_chunk(long long nd, int ns)
+{
+    // about 256 workgroups in total, chunks a multiple of the staged slice
+    const long long tiles = (long long)((ns + kRrTile - 1) / kRrTile) * ((ns + kRrTile - 1) / kRrTile);
+    long long nch = std::max<long long>(1, 512 / tiles);
+    long long c = (nd + nch - 1) / nch;
+    c = (c + kRrK - 1) / kRrK * kRrK;
+    return std::max<long long>(c, kRrK);
+}
+
 size_t sparc_rr_workspace_bytes(const sparc_op *op, int32_t dtype, int32_t ns)
 {
     if (!op || ns < 1) return 0;
     size_t b = 0;
     if (dtype == SPARC_F32) b += align_up((size_t)op->nd * ns * sizeof(double));  // promoted Y
     b += align_up((size_t)op->nd * ns * sizeof(double));                           // H Y
-    b += align_up((size_t)std::max(1, op->nproj_total) * ns * sizeof(double));     // gathered coefficients
+    b += gather_bytes(op, SPARC_F64, ns);                                           // gathered projections
     b += 2 * align_up((size_t)ns * ns * sizeof(double));                           // H_s, M_s
     b += 2 * align_up((size_t)ns * sizeof(double)) + align_up(sizeof(int));       // D, E, info
+    const long long nch = (op->nd + rr_chunk(op->nd, ns) - 1) / rr_chunk(op->nd, ns);
+    b += align_up((size_t)nch * 2 * ns * ns * sizeof(double));                     // projection partials
     return b;
 }
 
@@ -281,7 +441,6 @@ int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_
     if (!op || !Y || !theta) return fail(SPARC_E_ARG, "null argument");
     if (dtype != SPARC_F64 && dtype != SPARC_F32) return fail(SPARC_E_ARG, "bad dtype");
     if (ns < 1 || ldy < op->nd) return fail(SPARC_E_SHAPE, "ns < 1 or ldy < N_d");
-    if (ldy > 0x7fffffffLL || op->nd > 0x7fffffffLL) return fail(SPARC_E_SHAPE, "leading dimension exceeds 32 bits");
     const size_t need = sparc_rr_workspace_bytes(op, dtype, ns);
     if (!ws || ws_bytes < need) return fail(SPARC_E_WORKSPACE, "workspace too small");
     hipStream_t s = (hipStream_t)stream;
@@ -299,7 +458,7 @@ int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_
     double *HY = (double *)p;
     p += align_up((size_t)nd * ns * sizeof(double));
     double *G = (double *)p;
-    p += align_up((size_t)std::max(1, op->nproj_total) * ns * sizeof(double));
+    p += gather_bytes(op, SPARC_F64, ns);
     double *Hs = (double *)p;
     p += align_up((size_t)ns * ns * sizeof(double));
     double *Ms = (double *)p;
@@ -309,26 +468,29 @@ int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_
     double *E = (double *)p;
     p += align_up((size_t)ns * sizeof(double));
     int *info = (int *)p;
+    p += align_up(sizeof(int));
+    double *partial = (double *)p;
 
     int st;
     StepLaunch L = choose_step_launch(op, SPARC_F64, ns);
-    if ((st = launch_gather(op, SPARC_F64, Y64, ld64, ns, G, s))) return st;
     StepCoef hc{1.0, 0.0, 0.0, 0};
-    if ((st = launch_step(op, SPARC_F64, Y64, ld64, nullptr, 0, HY, nd, ns, G, hc, L, s))) return st;
+    if ((st = launch_h_step(op, SPARC_F64, Y64, ld64, nullptr, 0, HY, nd, ns, G, hc, L, s))) return st;
+
+    const long long kc = rr_chunk(nd, ns);
+    const int nch = (int)((nd + kc - 1) / kc);
+    const int nt = (ns + kRrTile - 1) / kRrTile;
+    hipLaunchKernelGGL(rr_project_kernel, dim3(nch, nt, nt), dim3(256), 0, s, Y64, ld64, HY, nd, nd, ns, kc, partial);
+    const long long tot = 2LL * ns * ns;
+    hipLaunchKernelGGL(rr_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, partial, nch, ns, Ms, Hs);
+    dim3 tb(16, 16), tg((ns + 15) / 16, (ns + 15) / 16);
+    hipLaunchKernelGGL(symmetrize, tg, tb, 0, s, Hs, ns);
+    hipLaunchKernelGGL(symmetrize, tg, tb, 0, s, Ms, ns);
+    SPARC_HIP(hipGetLastError());
 
     std::lock_guard<std::mutex> lk(g_blas_mu);
     rocblas_handle hb = blas_handle();
     if (!hb) return fail(SPARC_E_HIP, "rocblas_create_handle failed");
     rocblas_set_stream(hb, s);
-    const double one = 1.0, zero = 0.0;
-    if (rocblas_dgemm(hb, rocblas_operation_transpose, rocblas_operation_none, ns, ns, (int)nd, &one, Y64, (int)ld64,
-                      HY, (int)nd, &zero, Hs, ns) != rocblas_status_success ||
-        rocblas_dgemm(hb, rocblas_operation_transpose, rocblas_operation_none, ns, ns, (int)nd, &one, Y64, (int)ld64,
-                      Y64, (int)ld64, &zero, Ms, ns) != rocblas_status_success)
-        return fail(SPARC_E_HIP, "rocblas_dgemm failed");
-    dim3 tb(16, 16), tg((ns + 15) / 16, (ns + 15) / 16);
-    hipLaunchKernelGGL(symmetrize, tg, tb, 0, s, Hs, ns);
-    hipLaunchKernelGGL(symmetrize, tg, tb, 0, s, Ms, ns);
     if (rocsolver_dsygvd(hb, rocblas_eform_ax, evec ? rocblas_evect_original : rocblas_evect_none, rocblas_fill_upper,
                          ns, Hs, ns, Ms, ns, D, E, info) != rocblas_status_success)
         return fail(SPARC_E_HIP, "rocsolver_dsygvd failed");
