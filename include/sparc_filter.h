@@ -206,7 +206,7 @@ int sparc_profile_read(int32_t kernel, int64_t *launches, double *total_ms);
 int sparc_profile_reset(void);
 
 /* Override the launch configuration of the fused step kernel for one dtype:
- * tile extent along z and y (one of 32x32, 64x16, 64x8, 32x16) and the number
+ * tile extent along z and y (one of 32x16, 32x32, 32x48, 64x8, 64x16) and the number
  * of x-planes per workgroup (chunk_x <= 0: library choice).  tile_z = tile_y
  * = 0 restores the library's tile choice.  Results do not depend on the
  * configuration.  Not thread-safe against calls that use the op.

@@ -404,7 +404,7 @@ int sparc_op_set_launch(sparc_op *op, int32_t dtype, int32_t tile_z, int32_t til
     } else {
         int found = -1;
         for (int s = 0; s < kNumShapes; ++s)
-            if (kShapes[s].tz == tile_z && kShapes[s].ty() == tile_y) found = s;
+            if (kShapes[s].tz == tile_z && kShapes[s].ty() == tile_y && found < 0) found = s;
         if (found < 0) return fail(SPARC_E_ARG, "unsupported tile shape");
         op->tune_shape[dtype] = found;
     }

@@ -1,0 +1,224 @@
+// Small generalized symmetric-definite eigensolver on the device, FP64.
+//
+// Solves H_s q = theta M_s q (the subspace problem of Sec. 3.4, Eq.
+// SubspaceGeneralizedEigenproblem) for n <= kEigMax in a single workgroup
+// with every matrix in LDS:
+//   1. Cholesky factorisation M_s = L L^T (column by column);
+//   2. reduction to standard form C = L^{-1} H_s L^{-T} by two triangular
+//      solves (one thread per column);
+//   3. cyclic Jacobi on C with the round-robin (circle) ordering, so the n/2
+//      rotations of a round touch disjoint rows/columns and are applied in
+//      parallel; sweeps stop when the off-diagonal mass is below 1e-30 of the
+//      total (relative 1e-15 in norm) or after max_sweeps;
+//   4. eigenvalues sorted ascending (stable), eigenvectors back-transformed
+//      q = L^{-T} z so that Q^T M_s Q = I.
+// Rotation for the pair (p, q): tau = (c_qq - c_pp) / (2 c_pq),
+// t = sign(tau) / (|tau| + sqrt(1 + tau^2)), c = 1/sqrt(1 + t^2), s = t c;
+// rows and columns p, q are replaced by (c x_p - s x_q, s x_p + c x_q), which
+// zeroes c_pq.
+#include "internal.hpp"
+
+namespace sparc {
+
+constexpr int kEigMax = 64;
+constexpr int kEigThreads = 1024;
+
+__device__ inline double block_sum_eig(double v, double *red)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < kEigThreads / 64; ++w) t += red[w];
+    return t;
+}
+
+__global__ void __launch_bounds__(kEigThreads) small_sygv_kernel(const double *__restrict__ Hs,
+                                                                  const double *__restrict__ Ms, int n,
+                                                                  double *theta, double *evec, int *info,
+                                                                  int max_sweeps)
+{
+    __shared__ double C[kEigMax][kEigMax + 1];
+    __shared__ double Z[kEigMax][kEigMax + 1];
+    __shared__ double L[kEigMax][kEigMax + 1];
+    __shared__ double rc[kEigMax / 2], rs[kEigMax / 2];
+    __shared__ int rp[kEigMax / 2], rq[kEigMax / 2];
+    __shared__ double red[kEigThreads / 64];
+    __shared__ double lam[kEigMax];
+    __shared__ int rank[kEigMax];
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    const int nt = blockDim.x;
+
+    for (int e = tid; e < n * n; e += nt) {
+        const int i = e % n, j = e / n;  // column-major input
+        L[i][j] = Ms[(long long)j * n + i];
+        C[i][j] = Hs[(long long)j * n + i];
+    }
+    if (tid == 0) bad = 0;
+    __syncthreads();
+
+    // 1. Cholesky, lower triangle of L
+    for (int j = 0; j < n; ++j) {
+        if (tid == 0) {
+            const double d = L[j][j];
+            if (!(d > 0.0)) bad = j + 1;
+            L[j][j] = sqrt(d > 0.0 ? d : 1.0);
+        }
+        __syncthreads();
+        if (bad) break;
+        const double piv = L[j][j];
+        for (int i = j + 1 + tid; i < n; i += nt) L[i][j] /= piv;
+        __syncthreads();
+        const int m = n - j - 1;
+        for (int e = tid; e < m * m; e += nt) {
+            const int i = j + 1 + e / m, k = j + 1 + e % m;
+            if (k <= i) L[i][k] -= L[i][j] * L[k][j];
+        }
+        __syncthreads();
+    }
+    if (bad) {
+        if (tid == 0) info[0] = bad;
+        return;
+    }
+
+    // 2. W = L^{-1} H (columns), then C = L^{-1} W^T, held in Z then copied
+    if (tid < n) {
+        const int c = tid;
+        for (int i = 0; i < n; ++i) {
+            double s = C[i][c];
+            for (int k = 0; k < i; ++k) s -= L[i][k] * C[k][c];
+            C[i][c] = s / L[i][i];
+        }
+    }
+    __syncthreads();
+    if (tid < n) {
+        const int c = tid;
+        for (int i = 0; i < n; ++i) {
+            double s = C[c][i];
+            for (int k = 0; k < i; ++k) s -= L[i][k] * Z[k][c];
+            Z[i][c] = s / L[i][i];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < n * n; e += nt) {
+        const int i = e % n, j = e / n;
+        C[i][j] = 0.5 * (Z[i][j] + Z[j][i]);
+    }
+    __syncthreads();
+    for (int e = tid; e < n * n; e += nt) {
+        const int i = e % n, j = e / n;
+        Z[i][j] = i == j ? 1.0 : 0.0;
+    }
+    __syncthreads();
+
+    // 3. cyclic Jacobi, round-robin pairs over an even number of indices
+    const int np = n + (n & 1);
+    const int half = np / 2;
+    for (int sweep = 0; sweep < max_sweeps && n > 1; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int e = tid; e < n * n; e += nt) {
+            const int i = e % n, j = e / n;
+            const double v = C[i][j] * C[i][j];
+            tot += v;
+            if (i != j) off += v;
+        }
+        off = block_sum_eig(off, red);
+        tot = block_sum_eig(tot, red);
+        if (!(off > 1e-30 * tot)) break;
+        for (int r = 0; r < np - 1; ++r) {
+            if (tid < half) {
+                const int k = tid;
+                int p, q;
+                if (k == 0) {
+                    p = np - 1;
+                    q = r;
+                } else {
+                    p = (r + k) % (np - 1);
+                    q = (r - k + np - 1) % (np - 1);
+                }
+                if (p > q) {
+                    const int t = p;
+                    p = q;
+                    q = t;
+                }
+                double c = 1.0, s = 0.0;
+                const bool valid = q < n;
+                if (valid && C[p][q] != 0.0) {
+                    const double tau = (C[q][q] - C[p][p]) / (2.0 * C[p][q]);
+                    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + t * t);
+                    s = t * c;
+                }
+                rc[k] = c;
+                rs[k] = s;
+                rp[k] = valid ? p : -1;
+                rq[k] = q;
+            }
+            __syncthreads();
+            for (int e = tid; e < half * n; e += nt) {
+                const int k = e / n, j = e % n;
+                const int p = rp[k];
+                if (p < 0) continue;
+                const int q = rq[k];
+                const double c = rc[k], s = rs[k];
+                const double a = C[p][j], b = C[q][j];
+                C[p][j] = c * a - s * b;
+                C[q][j] = s * a + c * b;
+            }
+            __syncthreads();
+            for (int e = tid; e < half * n; e += nt) {
+                const int k = e / n, i = e % n;
+                const int p = rp[k];
+                if (p < 0) continue;
+                const int q = rq[k];
+                const double c = rc[k], s = rs[k];
+                const double a = C[i][p], b = C[i][q];
+                C[i][p] = c * a - s * b;
+                C[i][q] = s * a + c * b;
+                const double za = Z[i][p], zb = Z[i][q];
+                Z[i][p] = c * za - s * zb;
+                Z[i][q] = s * za + c * zb;
+            }
+            __syncthreads();
+        }
+    }
+
+    // 4. sort (stable ascending) and back-transform q = L^{-T} z
+    if (tid < n) lam[tid] = C[tid][tid];
+    __syncthreads();
+    if (tid < n) {
+        int rk = 0;
+        const double li = lam[tid];
+        for (int j = 0; j < n; ++j) rk += (lam[j] < li) || (lam[j] == li && j < tid);
+        rank[tid] = rk;
+        theta[rk] = li;
+    }
+    __syncthreads();
+    if (tid < n) {
+        const int c = tid;
+        for (int k = n - 1; k >= 0; --k) {
+            double s = Z[k][c];
+            for (int m = k + 1; m < n; ++m) s -= L[m][k] * C[m][c];
+            C[k][c] = s / L[k][k];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < n * n; e += nt) {
+        const int k = e % n, c = e / n;
+        evec[(long long)rank[c] * n + k] = C[k][c];
+    }
+    if (tid == 0) info[0] = 0;
+}
+
+int launch_small_sygv(const double *Hs, const double *Ms, int n, double *theta, double *evec, int *info,
+                      hipStream_t stream)
+{
+    if (n < 1 || n > kEigMax) return fail(SPARC_E_ARG, "small eigensolver needs 1 <= n <= 64");
+    hipLaunchKernelGGL(small_sygv_kernel, dim3(1), dim3(kEigThreads), 0, stream, Hs, Ms, n, theta, evec, info, 40);
+    SPARC_HIP(hipGetLastError());
+    return SPARC_OK;
+}
+
+}  // namespace sparc

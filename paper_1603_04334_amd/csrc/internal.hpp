@@ -28,14 +28,14 @@ struct AtomDev {
     long long chi0;   // offset of the atom's chi block (nproj * nbox values)
 };
 
-// Tile shapes of the fused step kernel: a workgroup owns a TY x TZ patch of
-// the (y, z) plane and streams it along x.  TZ lanes run along z; each thread
-// owns RY rows of y spaced 256/TZ apart.
+// Tile shapes of the fused step kernel: a workgroup of nt threads owns a
+// TY x TZ patch of the (y, z) plane and streams it along x.  TZ lanes run
+// along z; each thread owns RY consecutive rows of y.
 struct TileShape {
-    int tz, ry;
-    int ty() const { return ry * (kBlock / tz); }
+    int tz, ry, nt;
+    int ty() const { return ry * (nt / tz); }
 };
-constexpr int kNumShapes = 4;
+constexpr int kNumShapes = 6;
 extern const TileShape kShapes[kNumShapes];
 
 }  // namespace sparc
@@ -131,6 +131,11 @@ int launch_step(const sparc_op *op, int dtype, const void *yk, int64_t ldk, cons
 int launch_h_step(const sparc_op *op, int dtype, const void *yk, int64_t ldk, const void *yprev, int64_t ldp,
                   void *out, int64_t ldo, int ns, void *part, const StepCoef &c, const StepLaunch &L,
                   hipStream_t stream);
+
+// small generalized eigensolver (n <= 64) in one workgroup: theta ascending,
+// evec column-major and M-orthonormal; info = 0 or the failing Cholesky column
+int launch_small_sygv(const double *Hs, const double *Ms, int n, double *theta, double *evec, int *info,
+                      hipStream_t stream);
 
 // profiling hooks (no-ops unless enabled)
 struct ProfScope {

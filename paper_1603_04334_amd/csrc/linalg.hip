@@ -11,7 +11,8 @@
 // Rayleigh-Ritz (Sec. 3.4, Eq. SubspaceGeneralizedEigenproblem): the block is
 // promoted to FP64, H Y is formed by the fused kernel, H_s = Y^T (H Y) and
 // M_s = Y^T Y are plain FP64 GEMMs (rocBLAS), and the symmetric-definite
-// problem is solved on the device by rocSOLVER's dsygvd.
+// problem is solved on the device: in one workgroup (Cholesky + Jacobi) for
+// up to 64 columns, by rocSOLVER's dsygvd beyond.
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -487,13 +488,18 @@ int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_
     hipLaunchKernelGGL(symmetrize, tg, tb, 0, s, Ms, ns);
     SPARC_HIP(hipGetLastError());
 
-    std::lock_guard<std::mutex> lk(g_blas_mu);
-    rocblas_handle hb = blas_handle();
-    if (!hb) return fail(SPARC_E_HIP, "rocblas_create_handle failed");
-    rocblas_set_stream(hb, s);
-    if (rocsolver_dsygvd(hb, rocblas_eform_ax, evec ? rocblas_evect_original : rocblas_evect_none, rocblas_fill_upper,
-                         ns, Hs, ns, Ms, ns, D, E, info) != rocblas_status_success)
-        return fail(SPARC_E_HIP, "rocsolver_dsygvd failed");
+    if (ns <= 64) {
+        // one-workgroup Cholesky + Jacobi; eigenvectors land in Hs
+        if ((st = launch_small_sygv(Hs, Ms, ns, D, Hs, info, s))) return st;
+    } else {
+        std::lock_guard<std::mutex> lk(g_blas_mu);
+        rocblas_handle hb = blas_handle();
+        if (!hb) return fail(SPARC_E_HIP, "rocblas_create_handle failed");
+        rocblas_set_stream(hb, s);
+        if (rocsolver_dsygvd(hb, rocblas_eform_ax, evec ? rocblas_evect_original : rocblas_evect_none,
+                             rocblas_fill_upper, ns, Hs, ns, Ms, ns, D, E, info) != rocblas_status_success)
+            return fail(SPARC_E_HIP, "rocsolver_dsygvd failed");
+    }
     int hinfo = 0;
     SPARC_HIP(hipMemcpyAsync(theta, D, ns * sizeof(double), hipMemcpyDeviceToHost, s));
     SPARC_HIP(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -32,7 +32,8 @@
 
 namespace sparc {
 
-const TileShape kShapes[kNumShapes] = {{32, 4}, {64, 4}, {64, 2}, {32, 2}};
+const TileShape kShapes[kNumShapes] = {{32, 2, 256}, {32, 2, 512}, {32, 2, 768}, {64, 2, 256},
+                                       {64, 2, 512}, {32, 4, 256}};
 
 template <typename T>
 struct StepArgs {
@@ -49,16 +50,16 @@ struct StepArgs {
     T alpha, beta, shift;
 };
 
-template <typename T, int TZ, int RY, bool PREV>
+template <typename T, int TZ, int RY, int NT, bool PREV>
 struct StepKernel {
     static constexpr int R = kMaxRadius;
     static constexpr int QL = 2 * R + 1;     // queue length: planes x-R .. x+R
-    static constexpr int NYG = kBlock / TZ;
+    static constexpr int NYG = NT / TZ;
     static constexpr int TY = NYG * RY;
     static constexpr int SZ = TZ + 2 * R;
     static constexpr int SY = TY + 2 * R;
     static constexpr int NHALO = 2 * R * TZ + 2 * R * TY;
-    static constexpr int NH = (NHALO + kBlock - 1) / kBlock;
+    static constexpr int NH = (NHALO + NT - 1) / NT;
 
     // values loaded for one plane t: its halo, the queue heads (plane t+R),
     // V_eff and yprev at the thread's own points
@@ -195,7 +196,7 @@ struct StepKernel {
         }
 #pragma unroll
         for (int i = 0; i < NH; ++i) {
-            const int e = tid + i * kBlock;
+            const int e = tid + i * NT;
             int ly = -1, lzz = -1;
             if (e < 2 * R * TZ) {
                 const int hy = e / TZ, hz = e % TZ;
@@ -239,41 +240,38 @@ struct StepKernel {
     }
 };
 
-template <typename T, int TZ, int RY, bool PREV>
-__global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs<T> a)
+template <typename T, int TZ, int RY, int NT, bool PREV>
+__global__ void __launch_bounds__(NT) step_kernel(const StepArgs<T> a)
 {
-    StepKernel<T, TZ, RY, PREV> k(a);
+    StepKernel<T, TZ, RY, NT, PREV> k(a);
     k.run();
 }
 
 StepLaunch choose_step_launch(const sparc_op *op, int dtype, int ns)
 {
     StepLaunch L;
-    const int n3 = op->n[2];
-    // prefer a z extent that tiles n3 with little waste; two rows per thread
-    // keep the register footprint low enough for three or more waves per SIMD
-    const int waste32 = (32 - n3 % 32) % 32;
-    const int waste64 = (64 - n3 % 64) % 64;
-    L.shape = (n3 >= 64 && waste64 < waste32) ? 2 : 3;
+    // 32 x 16 patches of 256 threads measured fastest for both dtypes on the
+    // 96^3 and larger grids (lowest register footprint, 4-5 waves per SIMD)
+    L.shape = 0;
     if (op->tune_shape[dtype] >= 0) L.shape = op->tune_shape[dtype];
     const TileShape &s = kShapes[L.shape];
-    const long long tiles = (long long)((op->n[1] + s.ty() - 1) / s.ty()) * ((n3 + s.tz - 1) / s.tz);
-    const long long per_chunk = tiles * ns;
-    // split x when too few workgroups would fill the 256 CUs
-    int nchunks = 1;
-    while (per_chunk * nchunks < 2048 && op->n[0] / (nchunks * 2) >= 8) nchunks *= 2;
-    L.chunk_x = (op->n[0] + nchunks - 1) / nchunks;
+    const long long tiles = (long long)((op->n[1] + s.ty() - 1) / s.ty()) * ((op->n[2] + s.tz - 1) / s.tz);
+    const long long waves = tiles * ns * (s.nt / 64);
+    // split x so that about 8192 waves are in flight, keeping >= 4 planes per chunk
+    long long nchunks = (8192 + waves - 1) / waves;
+    nchunks = std::max<long long>(1, std::min<long long>(nchunks, op->n[0] / 4));
+    L.chunk_x = (int)((op->n[0] + nchunks - 1) / nchunks);
     if (op->tune_chunk[dtype] > 0) L.chunk_x = std::min(op->n[0], op->tune_chunk[dtype]);
     return L;
 }
 
-template <typename T, int TZ, int RY>
+template <typename T, int TZ, int RY, int NT>
 static int launch_typed(const StepArgs<T> &a, bool prev, hipStream_t stream)
 {
     if (prev)
-        hipLaunchKernelGGL((step_kernel<T, TZ, RY, true>), dim3(a.nblocks), dim3(kBlock), 0, stream, a);
+        hipLaunchKernelGGL((step_kernel<T, TZ, RY, NT, true>), dim3(a.nblocks), dim3(NT), 0, stream, a);
     else
-        hipLaunchKernelGGL((step_kernel<T, TZ, RY, false>), dim3(a.nblocks), dim3(kBlock), 0, stream, a);
+        hipLaunchKernelGGL((step_kernel<T, TZ, RY, NT, false>), dim3(a.nblocks), dim3(NT), 0, stream, a);
     SPARC_HIP(hipGetLastError());
     return SPARC_OK;
 }
@@ -310,10 +308,12 @@ static int launch_step_t(const sparc_op *op, const void *yk, int64_t ldk, const 
     a.shift = (T)c.shift;
     ProfScope prof(0, stream);
     switch (L.shape) {
-        case 0: return launch_typed<T, 32, 4>(a, prev, stream);
-        case 1: return launch_typed<T, 64, 4>(a, prev, stream);
-        case 2: return launch_typed<T, 64, 2>(a, prev, stream);
-        case 3: return launch_typed<T, 32, 2>(a, prev, stream);
+        case 0: return launch_typed<T, 32, 2, 256>(a, prev, stream);
+        case 1: return launch_typed<T, 32, 2, 512>(a, prev, stream);
+        case 2: return launch_typed<T, 32, 2, 768>(a, prev, stream);
+        case 3: return launch_typed<T, 64, 2, 256>(a, prev, stream);
+        case 4: return launch_typed<T, 64, 2, 512>(a, prev, stream);
+        case 5: return launch_typed<T, 32, 4, 256>(a, prev, stream);
     }
     return fail(SPARC_E_ARG, "unknown tile shape");
 }

@@ -237,3 +237,30 @@ def test_argument_errors(small):
     assert st == binding.SPARC_E_SHAPE
     st = lib.sparc_h_apply(op.handle, 7, Xd.data_ptr(), cl.nd, Y.data_ptr(), cl.nd, c.ns, ws.data_ptr(), ws.numel(), None)
     assert st == binding.SPARC_E_ARG
+
+
+@pytest.mark.parametrize("ns", [1, 7, 33, 64, 70])
+def test_rayleigh_ritz_sizes(ns):
+    # one-workgroup Jacobi path (ns <= 64) and library path (ns > 64)
+    cl = inputs.make_cluster(16, 0.5, 2, 4, 1, seed=21, min_dist=0.0, margin=3.0)
+    rng = np.random.default_rng(ns)
+    Y = rng.standard_normal((ns, cl.nd))
+    rt, _, Hs, Ms = oracle.rayleigh_ritz(cl, Y)
+    op = _b().Operator(cl)
+    theta, Qt = op.rayleigh_ritz(dev(Y))
+    assert np.abs(theta - rt).max() <= TOL_RITZ * max(1.0, np.abs(rt).max() * 1e-3)
+    Q = host(Qt).T
+    # M-orthonormal eigenvectors of the oracle's projected pencil
+    assert np.abs(Q.T @ Ms @ Q - np.eye(ns)).max() < 1e-9
+    assert np.abs(Hs @ Q - Ms @ Q * theta).max() < 1e-8 * max(1.0, np.abs(Hs).max())
+
+
+def test_lanczos_medium_grid():
+    c = inputs.MEDIUM
+    cl = inputs.case_cluster(c.name)
+    op = _b().Operator(cl)
+    v0 = inputs.lanczos_start(cl.nd, c.seed)
+    _, _, theta = op.lanczos(40, dev(v0))
+    _, _, rt = oracle.lanczos(cl, 40, v0)
+    print("medium lanczos max |dtheta|", np.abs(theta - rt).max())
+    assert np.abs(theta - rt).max() <= TOL_RITZ
