@@ -48,9 +48,9 @@ def source_hash() -> str:
     return hashlib.sha256(open(STENCIL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per step-kernel launch from committed counter runs, or None
-    when absent or taken on a different kernel source."""
+def read_traffic(dtype):
+    """HBM bytes per recurrence-step launch from committed counter runs, or
+    None when absent or taken on a different kernel source."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -61,7 +61,7 @@ def read_traffic():
     if kv.get("stencil_sha256_16") != source_hash():
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv[f"{dtype}_hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
 
@@ -131,14 +131,10 @@ def timed(fn, steps, warmup):
 
 
 def alg_bytes_per_step_launch(case, cl, s):
-    """Algorithmic HBM bytes of the fused step kernel averaged over one filter:
-    the first step reads X and writes Y_1; each later step reads Y_k and
-    Y_{k-1} and writes Y_{k+1}; plus one read of V_eff and of the projector
-    values per step."""
-    nd, ns, m = cl.nd, case.ns, case.m
-    streams = (2 + 3 * (m - 1)) / m
-    chi = sum(a.chi.size for a in cl.atoms)
-    return streams * s * nd * ns + s * nd + s * chi
+    """Algorithmic HBM bytes of one recurrence-step launch of the fused
+    kernel: read Y_k and Y_{k-1}, write Y_{k+1} (s bytes per orbital*gridpoint
+    each) and read V_eff once (s bytes per gridpoint)."""
+    return 3 * s * cl.nd * case.ns + s * cl.nd
 
 
 def cpu_baseline(case, cl):
@@ -184,11 +180,13 @@ def main():
     torch.cuda.synchronize()
     n_launch, ms = binding.profile.read(0)
     n_g, ms_g = binding.profile.read(1)
+    n_sc, ms_sc = binding.profile.read(2)
+    n_f, ms_f = binding.profile.read(3)
     binding.profile.reset()
     avg_s = ms / 1e3 / max(n_launch, 1)
     alg = alg_bytes_per_step_launch(case, cl, s)
     achieved = alg / avg_s / 1e9
-    traffic = read_traffic() if args.dtype == "f32" else None
+    traffic = read_traffic(args.dtype)
     t_filter = timed(main_pass.filter_only, args.steps, 1)
 
     out = {
@@ -211,10 +209,12 @@ def main():
         "filter_only": {"value": updates / t_filter, "ms": t_filter * 1e3},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "step_kernel (fused stencil+V+nonlocal scatter+recurrence)",
+                     "kernel": "step_kernel<T,32,2,256,prev> (fused stencil + local potential + recurrence)",
                      "launches": n_launch, "avg_launch_us": avg_s * 1e6,
                      "alg_bytes_per_launch": alg},
         "gather_kernel": {"launches": n_g, "avg_launch_us": ms_g / max(n_g, 1) * 1e3},
+        "scatter_kernel": {"launches": n_sc, "avg_launch_us": ms_sc / max(n_sc, 1) * 1e3},
+        "first_step_kernel": {"launches": n_f, "avg_launch_us": ms_f / max(n_f, 1) * 1e3},
         "bounds": list(main_pass.bounds),
     }
     tz, ty, cx = main_pass.op.step_config(main_pass.code, case.ns)

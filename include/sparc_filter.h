@@ -197,8 +197,9 @@ const char *sparc_status_str(int status);
 const char *sparc_last_error(void);
 
 /* Per-kernel timing with HIP events recorded around each launch on the
- * launching stream.  kernel: 0 = fused stencil/potential/recurrence step,
- * 1 = projector gather, 2 = projector scatter.  enable(1) starts recording;
+ * launching stream.  kernel: 0 = fused stencil/potential/recurrence step
+ * with Y_{k-1} (k >= 1), 1 = projector gather, 2 = projector scatter, 3 = the
+ * same fused step without Y_{k-1} (first filter step, H application).  enable(1) starts recording;
  * read() synchronises the recorded events and returns the number of launches
  * and their summed duration in ms; reset() clears the counts. */
 int sparc_profile_enable(int32_t on);

@@ -289,7 +289,8 @@ def rotate(Y, Qt, out=None, stream=None):
 
 
 class profile:
-    """Per-kernel HIP-event timing inside the library (0 = fused step, 1 = gather, 2 = scatter)."""
+    """Per-kernel HIP-event timing inside the library (0 = fused recurrence step,
+    1 = gather, 2 = scatter, 3 = fused step without Y_{k-1})."""
 
     @staticmethod
     def enable(on: bool = True):

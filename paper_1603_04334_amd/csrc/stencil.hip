@@ -306,7 +306,7 @@ static int launch_step_t(const sparc_op *op, const void *yk, int64_t ldk, const 
     a.alpha = (T)c.alpha;
     a.beta = (T)c.beta;
     a.shift = (T)c.shift;
-    ProfScope prof(0, stream);
+    ProfScope prof(prev ? 0 : 3, stream);
     switch (L.shape) {
         case 0: return launch_typed<T, 32, 2, 256>(a, prev, stream);
         case 1: return launch_typed<T, 32, 2, 512>(a, prev, stream);
