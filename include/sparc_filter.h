@@ -191,6 +191,54 @@ int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_
 int sparc_rotate(int32_t dtype, const void *Y, int64_t ldy, int64_t nd, int32_t ns, const double *Q,
                  void *out, int64_t ldo, void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------- batched filters */
+
+/* One filter of a batch: the arguments of sparc_cheb_filter for one cluster.
+ * X and Y stay owned by the caller and must stay allocated while the batch
+ * exists; the batch owns the workspaces. */
+typedef struct {
+    const sparc_op *op;
+    int32_t dtype;
+    const void *X;
+    int64_t ldx;
+    void *Y;
+    int64_t ldy;
+    int32_t ns;
+    int32_t m;
+    double a0, a, b;
+} sparc_batch_job;
+
+typedef struct sparc_batch sparc_batch;
+
+/* Build a batch of Chebyshev filters over uneven clusters (Sec. 3.4 applied
+ * to each job).  Every filter is cut into the work items of its degree steps
+ * (projector gather and stencil patches of step k, then the projector scatter
+ * of step k), items are ordered level by level across the batch, and
+ *   mode 0: one persistent launch takes items from an atomic ticket and waits
+ *           per cluster for the items each depends on (device-scope
+ *           release/acquire counters, bounded waits), captured together with
+ *           the counter reset in a HIP graph that later runs replay;
+ *   mode 1: the same persistent launch without the graph;
+ *   mode 2: one grouped launch per level (no waits);
+ *   mode 3: the plain filters one after another.
+ * Every mode gives each job exactly the result of sparc_cheb_filter.
+ * Allocates the per-job workspaces and the schedule on the current device.
+ * Errors: SPARC_E_ARG, SPARC_E_BOUNDS, SPARC_E_SHAPE, SPARC_E_NOMEM, SPARC_E_HIP. */
+int sparc_batch_create(const sparc_batch_job *jobs, int32_t njobs, int32_t mode, sparc_batch **out);
+
+/* Enqueue one run of the whole batch on stream.  Asynchronous. */
+int sparc_batch_run(sparc_batch *batch, void *stream);
+
+/* Wait for stream and report whether the last run aborted (a dependency wait
+ * exceeded its bound; results are then invalid): SPARC_OK or SPARC_E_JOB. */
+int sparc_batch_check(sparc_batch *batch, void *stream, int32_t *aborted);
+
+/* Work items, levels and persistent grid size of a batch (out params may be NULL). */
+int sparc_batch_info(const sparc_batch *batch, int64_t *items, int32_t *levels, int32_t *grid);
+
+/* Free the batch (its graph, schedule and workspaces).  NULL is accepted. */
+int sparc_batch_destroy(sparc_batch *batch);
+
 /* ------------------------------------------------------------- diagnostics */
 
 const char *sparc_status_str(int status);

@@ -44,6 +44,12 @@ class sparc_atom(ctypes.Structure):
                 ("chi", ctypes.POINTER(ctypes.c_double)), ("gamma", ctypes.POINTER(ctypes.c_double))]
 
 
+class sparc_batch_job(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("X", ctypes.c_void_p), ("ldx", ctypes.c_int64),
+                ("Y", ctypes.c_void_p), ("ldy", ctypes.c_int64), ("ns", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("a0", ctypes.c_double), ("a", ctypes.c_double), ("b", ctypes.c_double)]
+
+
 _lib = None
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -73,6 +79,11 @@ _SIGS = {
     "sparc_profile_read": (_i32, [_i32, ctypes.POINTER(_i64), _dp]),
     "sparc_profile_reset": (_i32, []),
     "sparc_op_set_launch": (_i32, [_vp, _i32, _i32, _i32, _i32]),
+    "sparc_batch_create": (_i32, [ctypes.POINTER(sparc_batch_job), _i32, _i32, ctypes.POINTER(_vp)]),
+    "sparc_batch_run": (_i32, [_vp, _vp]),
+    "sparc_batch_check": (_i32, [_vp, _vp, ctypes.POINTER(_i32)]),
+    "sparc_batch_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "sparc_batch_destroy": (_i32, [_vp]),
     "sparc_step_config": (_i32, [_vp, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
 }
 
@@ -286,6 +297,58 @@ def rotate(Y, Qt, out=None, stream=None):
     check(lib().sparc_rotate(dt, _ptr(Y), ldy, nd, ns, _ptr(Qt), _ptr(out), out.stride(0), _ptr(ws), ws.numel(),
                              _stream(stream)), "sparc_rotate")
     return out
+
+
+class Batch:
+    """A batch of Chebyshev filters (one per job) run as one unit.
+
+    jobs: sequence of (Operator, X, Y, m, a0, a, b) with X, Y device blocks of
+    the same dtype.  mode: 0 persistent + HIP graph, 1 persistent, 2 one grouped
+    launch per level, 3 the plain filters one after another."""
+
+    def __init__(self, jobs, mode: int = 0):
+        arr = (sparc_batch_job * len(jobs))()
+        self._refs = []
+        for i, (op, X, Y, m, a0, a, b) in enumerate(jobs):
+            ns, ldx = _block(X, op.nd, "X")
+            _, ldy = _block(Y, op.nd, "Y")
+            arr[i].op = op.handle
+            arr[i].dtype = _dtype_code(X)
+            arr[i].X = _ptr(X)
+            arr[i].ldx = ldx
+            arr[i].Y = _ptr(Y)
+            arr[i].ldy = ldy
+            arr[i].ns = ns
+            arr[i].m = int(m)
+            arr[i].a0, arr[i].a, arr[i].b = float(a0), float(a), float(b)
+            self._refs += [op, X, Y]
+        h = _vp()
+        check(lib().sparc_batch_create(arr, len(jobs), int(mode), ctypes.byref(h)), "sparc_batch_create")
+        self.handle = h
+
+    def run(self, stream=None):
+        check(lib().sparc_batch_run(self.handle, _stream(stream)), "sparc_batch_run")
+
+    def check(self, stream=None) -> int:
+        ab = _i32()
+        lib().sparc_batch_check(self.handle, _stream(stream), ctypes.byref(ab))
+        return ab.value
+
+    def info(self):
+        items, levels, grid = _i64(), _i32(), _i32()
+        check(lib().sparc_batch_info(self.handle, ctypes.byref(items), ctypes.byref(levels), ctypes.byref(grid)))
+        return items.value, levels.value, grid.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().sparc_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class profile:

@@ -1,0 +1,79 @@
+"""Batched filters over uneven clusters: every mode reproduces the standalone
+filter bit for bit (the items run the same arithmetic), and sampled results
+agree with the CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1603_04334_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+# (grid, h, atoms, lmax, ns, m, dtype)
+JOBS = [
+    ((20, 20, 20), 0.45, 2, 1, 16, 16, torch.float32),
+    ((24, 28, 32), 0.45, 3, 1, 24, 21, torch.float32),
+    ((32, 32, 32), 0.45, 4, 1, 40, 17, torch.float32),
+    ((16, 18, 20), 0.5, 0, 1, 9, 12, torch.float32),    # no atoms
+    ((22, 22, 22), 0.45, 2, 2, 17, 19, torch.float64),
+    ((26, 20, 24), 0.45, 3, 1, 33, 8, torch.float64),
+]
+
+
+def _setup():
+    from paper_1603_04334_amd import binding
+    binding.lib()
+    jobs = []
+    for idx, (n, h, natoms, lmax, ns, m, dt) in enumerate(JOBS):
+        if natoms:
+            cl = inputs.make_cluster(n, h, natoms, 8, lmax, seed=40 + idx, min_dist=0.0, margin=3.0)
+        else:
+            cl = inputs.free_cluster(n, h, v0=-0.2)
+        X = inputs.orbitals(cl.nd, ns, seed=40 + idx)
+        if dt == torch.float32:
+            X = inputs.round_to_f32(X)
+        op = binding.Operator(cl)
+        a0, a, b = -3.0 - 0.1 * idx, 1.0 + 0.2 * idx, oracle.upper_bound(cl)
+        Xd = torch.from_numpy(X).to(dt).cuda()
+        ref = op.cheb_filter(Xd, m, a0, a, b)
+        jobs.append(dict(cl=cl, X=X, Xd=Xd, op=op, m=m, bounds=(a0, a, b), ref=ref, dt=dt))
+    torch.cuda.synchronize()
+    return binding, jobs
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+def test_batch_bitwise_equals_standalone(mode):
+    binding, jobs = _setup()
+    outs = [torch.full_like(j["Xd"], float("nan")) for j in jobs]
+    batch = binding.Batch([(j["op"], j["Xd"], o, j["m"], *j["bounds"]) for j, o in zip(jobs, outs)], mode=mode)
+    for rep in range(2):  # the second run replays the captured graph in mode 0
+        for o in outs:
+            o.fill_(float("nan"))
+        batch.run()
+        assert batch.check() == 0
+        torch.cuda.synchronize()
+        for j, o in zip(jobs, outs):
+            assert torch.equal(o, j["ref"]), (mode, rep, j["cl"].n)
+    items, levels, grid = batch.info()
+    assert items > 0 and levels == 2 * max(j["m"] for j in jobs)
+    batch.close()
+
+
+def test_batch_against_oracle_sampled():
+    binding, jobs = _setup()
+    outs = [torch.empty_like(j["Xd"]) for j in jobs]
+    batch = binding.Batch([(j["op"], j["Xd"], o, j["m"], *j["bounds"]) for j, o in zip(jobs, outs)], mode=0)
+    batch.run()
+    assert batch.check() == 0
+    for j, o in zip(jobs, outs):
+        got = o[:2].double().cpu().numpy()
+        if j["dt"] == torch.float32:
+            ref = oracle.cheb_filter(inputs.round_cluster_f32(j["cl"]), j["X"][:2], j["m"], *j["bounds"])
+            tol = 5e-5
+        else:
+            ref = oracle.cheb_filter(j["cl"], j["X"][:2], j["m"], *j["bounds"])
+            tol = 1e-12
+        err = (np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)).max()
+        assert err <= tol, (j["cl"].n, err)
+    batch.close()
