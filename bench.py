@@ -39,6 +39,8 @@ def parse():
     p.add_argument("--dtype", choices=["f32", "f64"], default="f32")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fp64-compare", action="store_true")
+    p.add_argument("--no-batch", action="store_true", help="skip the batched uneven-cluster measurement")
+    p.add_argument("--batch-only", action="store_true", help="print only the batched measurement")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run only a plain device copy of known size (for counter calibration)")
     return p.parse_args()
@@ -137,6 +139,55 @@ def alg_bytes_per_step_launch(case, cl, s):
     return 3 * s * cl.nd * case.ns + s * cl.nd
 
 
+def batch_measure(reps=5, nclusters=64):
+    """Batched uneven clusters (grid edge in {32..96}, h = 0.45, 2-24 atoms,
+    16-128 orbitals, degree 16-28), FP32 with FP64 coefficients.  Bounds come
+    from the device Lanczos (setup, untimed); orbitals are seeded N(0,1) drawn
+    on the device.  Returns throughput of each execution mode and of the plain
+    unbatched FP64 filters on the same clusters."""
+    import torch
+    from paper_1603_04334_amd import binding, inputs
+    recipe = inputs.batch_recipe(nclusters=nclusters)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4)
+    jobs32, jobs64, ops, work = [], [], [], 0
+    for r in recipe:
+        cl = inputs.make_cluster(r["n"], r["h"], r["natoms"], r["zmax"], r["lmax"], r["seed"])
+        op = binding.Operator(cl)
+        _, _, theta = op.lanczos(KSTEPS_LANCZOS, torch.from_numpy(inputs.lanczos_start(cl.nd, r["seed"])).cuda())
+        a0, a, b = binding.select_bounds(theta, 8, ubound=op.upper_bound())
+        op.autotune(binding.SPARC_F32, r["ns"])
+        X = torch.randn((r["ns"], cl.nd), generator=gen, device="cuda", dtype=torch.float32)
+        jobs32.append((op, X, torch.empty_like(X), r["m"], a0, a, b))
+        X64 = X.double()
+        jobs64.append((op, X64, torch.empty_like(X64), r["m"], a0, a, b))
+        ops.append(op)
+        work += cl.nd * r["ns"] * r["m"]
+    out = {"workload": f"{nclusters} uneven clusters, grid edge 32-96, h=0.45, 16-128 orbitals, degree 16-28",
+           "updates_per_run": work}
+    for name, jobs, mode in (("persistent_graph_f32", jobs32, 0), ("grouped_levels_graph_f32", jobs32, 4),
+                             ("sequential_f32", jobs32, 3), ("sequential_f64", jobs64, 3)):
+        bt = binding.Batch(jobs, mode=mode)
+        bt.run()
+        if bt.check():
+            raise RuntimeError("batch aborted")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            bt.run()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        if bt.check():
+            raise RuntimeError("batch aborted")
+        out[name] = {"ms": dt * 1e3, "value": work / dt}
+        if mode == 0:
+            out["items"], out["levels"], out["grid"] = bt.info()
+        bt.close()
+    for k in ("persistent_graph_f32", "grouped_levels_graph_f32", "sequential_f32"):
+        out[k]["vs_sequential_f64"] = out[k]["value"] / out["sequential_f64"]["value"]
+    return out
+
+
 def cpu_baseline(case, cl):
     import oracle
     from paper_1603_04334_amd import inputs
@@ -164,6 +215,9 @@ def main():
         return
     from paper_1603_04334_amd import binding, inputs
     binding.lib()
+    if args.batch_only:
+        print(json.dumps(batch_measure()), flush=True)
+        return
     case = inputs.MEDIUM
     cl = inputs.case_cluster(case.name)
     s = 4 if args.dtype == "f32" else 8
@@ -228,6 +282,9 @@ def main():
         out["fp64"] = {"value": updates / t64, "ms_per_step": t64 * 1e3, "filter_only": updates / t64f,
                        "filter_ms": t64f * 1e3}
         del p64
+    if not args.no_batch:
+        torch.cuda.empty_cache()
+        out["batched"] = batch_measure()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, cl)
     print(json.dumps(out), flush=True)

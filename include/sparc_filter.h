@@ -220,7 +220,8 @@ typedef struct sparc_batch sparc_batch;
  *           the counter reset in a HIP graph that later runs replay;
  *   mode 1: the same persistent launch without the graph;
  *   mode 2: one grouped launch per level (no waits);
- *   mode 3: the plain filters one after another.
+ *   mode 3: the plain filters one after another;
+ *   mode 4: mode 2 captured in a HIP graph (replayed on later runs).
  * Every mode gives each job exactly the result of sparc_cheb_filter.
  * Allocates the per-job workspaces and the schedule on the current device.
  * Errors: SPARC_E_ARG, SPARC_E_BOUNDS, SPARC_E_SHAPE, SPARC_E_NOMEM, SPARC_E_HIP. */
@@ -261,6 +262,17 @@ int sparc_profile_reset(void);
  * configuration.  Not thread-safe against calls that use the op.
  * Errors: SPARC_E_ARG (null op, bad dtype, unsupported tile). */
 int sparc_op_set_launch(sparc_op *op, int32_t dtype, int32_t tile_z, int32_t tile_y, int32_t chunk_x);
+
+/* Measure every tile shape and a few x-chunk lengths of the fused step kernel
+ * for this op, dtype and column count on scratch blocks (allocated and freed
+ * here), apply the fastest to the op as sparc_op_set_launch would, and return
+ * it (out params may be NULL; best_us = microseconds per recurrence step).
+ * Results are cached per (grid, ns, dtype) in the process and, when the
+ * environment variable SPARC_TUNE_CACHE names a file, appended to and read
+ * from that file.  Synchronous.  Not thread-safe against calls using the op.
+ * Errors: SPARC_E_ARG, SPARC_E_NOMEM, SPARC_E_HIP. */
+int sparc_autotune(sparc_op *op, int32_t dtype, int32_t ns, void *stream, int32_t *tile_z, int32_t *tile_y,
+                   int32_t *chunk_x, double *best_us);
 
 /* Launch configuration of the fused step kernel for a dtype and ns: tile
  * extent along z and y and the x-chunk length, as chosen by the library for

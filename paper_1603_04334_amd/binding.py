@@ -79,6 +79,8 @@ _SIGS = {
     "sparc_profile_read": (_i32, [_i32, ctypes.POINTER(_i64), _dp]),
     "sparc_profile_reset": (_i32, []),
     "sparc_op_set_launch": (_i32, [_vp, _i32, _i32, _i32, _i32]),
+    "sparc_autotune": (_i32, [_vp, _i32, _i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                              _dp]),
     "sparc_batch_create": (_i32, [ctypes.POINTER(sparc_batch_job), _i32, _i32, ctypes.POINTER(_vp)]),
     "sparc_batch_run": (_i32, [_vp, _vp]),
     "sparc_batch_check": (_i32, [_vp, _vp, ctypes.POINTER(_i32)]),
@@ -268,6 +270,13 @@ class Operator:
     def set_launch(self, dtype_code: int, tile_z: int = 0, tile_y: int = 0, chunk_x: int = 0):
         check(lib().sparc_op_set_launch(self.handle, dtype_code, tile_z, tile_y, chunk_x), "sparc_op_set_launch")
 
+    def autotune(self, dtype_code: int, ns: int, stream=None):
+        tz, ty, cx = _i32(), _i32(), _i32()
+        us = ctypes.c_double()
+        check(lib().sparc_autotune(self.handle, dtype_code, ns, _stream(stream), ctypes.byref(tz), ctypes.byref(ty),
+                                   ctypes.byref(cx), ctypes.byref(us)), "sparc_autotune")
+        return tz.value, ty.value, cx.value, us.value
+
     def step_config(self, dtype_code: int, ns: int):
         tz, ty, cx = _i32(), _i32(), _i32()
         check(lib().sparc_step_config(self.handle, dtype_code, ns, ctypes.byref(tz), ctypes.byref(ty),
@@ -304,7 +313,8 @@ class Batch:
 
     jobs: sequence of (Operator, X, Y, m, a0, a, b) with X, Y device blocks of
     the same dtype.  mode: 0 persistent + HIP graph, 1 persistent, 2 one grouped
-    launch per level, 3 the plain filters one after another."""
+    launch per level, 3 the plain filters one after another, 4 mode 2 in a HIP
+    graph."""
 
     def __init__(self, jobs, mode: int = 0):
         arr = (sparc_batch_job * len(jobs))()

@@ -2,9 +2,9 @@
 //
 // Every filter of the batch is cut into work items of the same three kinds a
 // standalone filter launches per degree step k (Sec. 3.4, Alg. 2):
-//   A(k): projector-gather items (atom, 16 columns, split) and stencil items
-//         (patch, x-chunk, column) of step k;
-//   B(k): projector-scatter items (node block, 4 columns) of step k.
+//   A(k): projector-gather items (atom, split; all column blocks) and stencil
+//         items (patch, x-chunk, group of 8 columns) of step k;
+//   B(k): projector-scatter items (node block; all column groups) of step k.
 // Dependencies per cluster: A(k) needs B(k-1) complete (A(k-1) when the cluster
 // has no atoms), B(k) needs A(k) complete.  Items are numbered in level order
 // (level 2k = A(k) of every cluster, level 2k+1 = B(k) of every cluster), and
@@ -14,8 +14,8 @@
 // the grid size.  Each wait is additionally bounded; on timeout the batch
 // raises an abort flag, every workgroup drains, and the host reports an error.
 //
-// Completion is published with a device-scope release (fence in every thread,
-// barrier, counter increment) and observed with a device-scope acquire, so
+// Completion is published with a device-scope release (barrier, then one
+// release increment of the counter) and observed with a device-scope acquire, so
 // data written on one XCD is read correctly on another.  Each item runs exactly
 // the arithmetic of the corresponding standalone kernel, so a cluster's result
 // is bit-identical alone and in the batch.
@@ -23,7 +23,8 @@
 // Modes: 0 = persistent kernel captured with the counter reset in a HIP graph
 // (replayed on later runs); 1 = the same two launches without a graph;
 // 2 = one grouped launch per level (kernel boundaries as barriers, no waits);
-// 3 = the plain per-cluster filters one after another (reference).
+// 3 = the plain per-cluster filters one after another (reference);
+// 4 = mode 2 captured in a HIP graph.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -85,67 +86,97 @@ using BStep = StepKernel<T, kBatchTZ, kBatchRY, kBatchNT, true>;
 template <typename T>
 using BStep0 = StepKernel<T, kBatchTZ, kBatchRY, kBatchNT, false>;
 
-template <typename T>
-__device__ void run_item(const BatchClusterDev &c, int kind, int k, int local, char *smem)
+constexpr int kBatchColGroup = 8;  // columns per stencil item
+
+struct StepSel {
+    const void *yk, *yprev;
+    void *out;
+    long long ldk, ldp, ldo;
+};
+
+__device__ inline StepSel select_buffers(const BatchClusterDev &c, int k)
 {
-    const double *cf = c.coef + 3 * k;
+    StepSel s;
     const bool odd_next = ((k + 1) & 1) != 0;
-    void *out = odd_next ? c.P : c.Q;
-    const long long ldo = odd_next ? c.ldp : c.ldq;
-    const void *yk = k == 0 ? c.X : ((k & 1) ? c.P : c.Q);
-    const long long ldk = k == 0 ? c.ldx : ((k & 1) ? c.ldp : c.ldq);
-    if (kind == 0) {
-        if (local < c.nG) {
-            GatherArgs<T> g;
-            g.Y = (const T *)yk;
-            g.ldy = ldk;
-            g.ns = c.ns;
-            g.nproj_total = c.nproj_total;
-            g.atoms = c.atoms;
-            g.box_off = c.box_off;
-            g.chi = (const T *)c.chi;
-            g.part = (T *)c.G;
-            const int per_atom = c.ncb * kGatherSplit;
-            const int atom = local / per_atom;
-            const int rem = local - atom * per_atom;
-            gather_item<T>(g, atom, rem / kGatherSplit, rem % kGatherSplit, (T(*)[16][16])smem);
-            return;
-        }
-        StepArgs<T> a;
-        a.yk = (const T *)yk;
-        a.yprev = (const T *)out;  // Y_{k-1} is overwritten in place
-        a.out = (T *)out;
-        a.veff = (const T *)c.veff;
-        a.ldk = ldk;
-        a.ldp = k == 1 ? c.ldx : ldo;
-        a.ldo = ldo;
-        if (k == 1) a.yprev = (const T *)c.X;
-        a.n1 = c.n1;
-        a.n2 = c.n2;
-        a.n3 = c.n3;
-        a.tiles_y = c.tiles_y;
-        a.tiles_z = c.tiles_z;
-        a.nchunks = c.nchunks;
-        a.chunk_x = c.chunk_x;
-        a.nblocks = c.nS;
-        a.c0 = (T)c.c0;
-        for (int p = 0; p < kMaxRadius; ++p) a.cp[p] = (T)c.cp[p];
-        a.alpha = (T)cf[0];
-        a.beta = (T)cf[1];
-        a.shift = (T)cf[2];
-        const int b = local - c.nG;
-        if (k == 0) {
-            BStep0<T> s(a);
-            s.run(b, (T(*)[BStep0<T>::SY * BStep0<T>::SZ])smem);
-        } else {
-            BStep<T> s(a);
-            s.run(b, (T(*)[BStep<T>::SY * BStep<T>::SZ])smem);
-        }
-        return;
+    s.out = odd_next ? c.P : c.Q;
+    s.ldo = odd_next ? c.ldp : c.ldq;
+    s.yk = k == 0 ? c.X : ((k & 1) ? c.P : c.Q);
+    s.ldk = k == 0 ? c.ldx : ((k & 1) ? c.ldp : c.ldq);
+    s.yprev = k == 1 ? c.X : s.out;  // Y_{k-1}, overwritten in place from k = 2 on
+    s.ldp = k == 1 ? c.ldx : s.ldo;
+    return s;
+}
+
+// projector gather of step k: item = (atom, split), all column blocks
+template <typename T>
+__device__ __forceinline__ void do_gather(const BatchClusterDev &c, int k, int local, char *smem)
+{
+    const StepSel sel = select_buffers(c, k);
+    GatherArgs<T> g;
+    g.Y = (const T *)sel.yk;
+    g.ldy = sel.ldk;
+    g.ns = c.ns;
+    g.nproj_total = c.nproj_total;
+    g.atoms = c.atoms;
+    g.box_off = c.box_off;
+    g.chi = (const T *)c.chi;
+    g.part = (T *)c.G;
+    const int atom = local / kGatherSplit, ks = local % kGatherSplit;
+#pragma unroll 1
+    for (int cb = 0; cb < c.ncb; ++cb) {
+        gather_item<T>(g, atom, cb, ks, (T(*)[16][16])smem);
+        __syncthreads();
     }
+}
+
+// stencil of step k: item = (patch, x-chunk, group of kBatchColGroup columns)
+template <typename T, bool PREV>
+__device__ __forceinline__ void do_step(const BatchClusterDev &c, int k, int local, char *smem)
+{
+    using K = StepKernel<T, kBatchTZ, kBatchRY, kBatchNT, PREV>;
+    const StepSel sel = select_buffers(c, k);
+    StepArgs<T> a;
+    a.yk = (const T *)sel.yk;
+    a.yprev = (const T *)sel.yprev;
+    a.out = (T *)sel.out;
+    a.veff = (const T *)c.veff;
+    a.ldk = sel.ldk;
+    a.ldp = sel.ldp;
+    a.ldo = sel.ldo;
+    a.n1 = c.n1;
+    a.n2 = c.n2;
+    a.n3 = c.n3;
+    a.tiles_y = c.tiles_y;
+    a.tiles_z = c.tiles_z;
+    a.nchunks = c.nchunks;
+    a.chunk_x = c.chunk_x;
+    a.nblocks = c.nS;
+    a.remap = 0;
+    a.c0 = (T)c.c0;
+    for (int p = 0; p < kMaxRadius; ++p) a.cp[p] = (T)c.cp[p];
+    const double *cf = c.coef + 3 * k;
+    a.alpha = (T)cf[0];
+    a.beta = (T)cf[1];
+    a.shift = (T)cf[2];
+    const int per_col = c.tiles_y * c.tiles_z * c.nchunks;
+    const int tc = local % per_col, g = local / per_col;
+    const int c1 = min(c.ns, (g + 1) * kBatchColGroup);
+#pragma unroll 1
+    for (int col = g * kBatchColGroup; col < c1; ++col) {
+        K s(a);
+        s.run(col * per_col + tc, (T(*)[K::SY * K::SZ])smem);
+        __syncthreads();
+    }
+}
+
+// projector scatter of step k: item = node block, all column groups
+template <typename T>
+__device__ __forceinline__ void do_scatter(const BatchClusterDev &c, int k, int local, char *smem)
+{
+    const StepSel sel = select_buffers(c, k);
     ScatterArgs<T> sa;
-    sa.out = (T *)out;
-    sa.ldo = ldo;
+    sa.out = (T *)sel.out;
+    sa.ldo = sel.ldo;
     sa.ns = c.ns;
     sa.nproj_total = c.nproj_total;
     sa.blk_pt = c.blk_pt;
@@ -158,11 +189,28 @@ __device__ void run_item(const BatchClusterDev &c, int kind, int k, int local, c
     sa.chi = (const T *)c.chi;
     sa.hg = (const T *)c.hg;
     sa.part = (const T *)c.G;
-    sa.alpha = (T)cf[0];
-    scatter_item<T>(sa, local / c.ncg, local % c.ncg, (T(*)[kMaxProj][kScatterCols])smem);
+    sa.alpha = (T)c.coef[3 * k];
+#pragma unroll 1
+    for (int cg = 0; cg < c.ncg; ++cg) {
+        scatter_item<T>(sa, local, cg, (T(*)[kMaxProj][kScatterCols])smem);
+        __syncthreads();
+    }
 }
 
-__device__ inline int find_segment(const BatchSegment *seg, int nseg, long long t)
+template <typename T>
+__device__ __forceinline__ void run_item(const BatchClusterDev &c, int kind, int k, int local, char *smem)
+{
+    if (kind == 1)
+        do_scatter<T>(c, k, local, smem);
+    else if (local < c.nG)
+        do_gather<T>(c, k, local, smem);
+    else if (k == 0)
+        do_step<T, false>(c, k, local - c.nG, smem);
+    else
+        do_step<T, true>(c, k, local - c.nG, smem);
+}
+
+__device__ inline int find_segment(const BatchSegment *seg, int nseg, int t)
 {
     int lo = 0, hi = nseg - 1;
     while (lo < hi) {
@@ -181,24 +229,26 @@ template <bool F32, bool F64>
 __global__ void __launch_bounds__(kBatchNT) batch_kernel(const BatchArgs args)
 {
     __shared__ __align__(16) char smem[kBatchLds];
-    __shared__ long long s_t;
+    __shared__ int s_t;
     __shared__ int s_go;
     const int tid = threadIdx.x;
     for (;;) {
         if (tid == 0) {
             if (args.waits)
                 s_t = __hip_atomic_load(args.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                          ? args.total
-                          : (long long)atomicAdd(args.ticket, 1u);
+                          ? (int)args.total
+                          : (int)atomicAdd(args.ticket, 1u);
             else
-                s_t = args.base + blockIdx.x;
+                s_t = (int)args.base + (int)blockIdx.x;
         }
         __syncthreads();
-        const long long t = s_t;
-        if (t >= args.total || (!args.waits && t >= args.base + (long long)gridDim.x)) break;
+        // the ticket is the same for the whole workgroup: make that explicit so
+        // the schedule and cluster descriptor are read with scalar loads
+        const int t = __builtin_amdgcn_readfirstlane(s_t);
+        if (t >= args.total) break;
         const BatchSegment sg = args.seg[find_segment(args.seg, args.nseg, t)];
         const BatchClusterDev &c = args.cl[sg.cluster];
-        const int local = (int)(t - sg.start);
+        const int local = t - (int)sg.start;
         if (args.waits) {
             if (tid == 0) {
                 const int *cnt = nullptr;
@@ -243,7 +293,8 @@ __global__ void __launch_bounds__(kBatchNT) batch_kernel(const BatchArgs args)
         if (F64 && c.dtype == SPARC_F64) run_item<double>(c, sg.kind, sg.step, local, smem);
         if (!args.waits) break;  // grouped launch: one item per workgroup
         {
-            __threadfence();
+            // every wave's stores have completed to L2 at the barrier; one
+            // device-scope release then publishes them with the count
             __syncthreads();
             if (tid == 0) {
                 int *cnt = (sg.kind == 0 ? c.cntA : c.cntB) + sg.step;
@@ -300,7 +351,7 @@ int batch_enqueue(sparc_batch *b, hipStream_t s)
     a.spin_limit = 1LL << 22;
     hipLaunchKernelGGL(zero_ints, dim3((unsigned)std::min<long long>(1024, (b->nints + 255) / 256)), dim3(256), 0, s,
                        b->d_ints, b->nints);
-    if (b->mode == 2) {
+    if (b->mode == 2 || b->mode == 4) {
         a.waits = 0;
         for (size_t L = 0; L + 1 < b->level_start.size(); ++L) {
             const long long n = b->level_start[L + 1] - b->level_start[L];
@@ -334,7 +385,7 @@ extern "C" {
 
 int sparc_batch_create(const sparc_batch_job *jobs, int32_t njobs, int32_t mode, sparc_batch **out)
 {
-    if (!jobs || njobs < 1 || !out || mode < 0 || mode > 3) return fail(SPARC_E_ARG, "bad batch arguments");
+    if (!jobs || njobs < 1 || !out || mode < 0 || mode > 4) return fail(SPARC_E_ARG, "bad batch arguments");
     *out = nullptr;
     sparc_batch *b = new (std::nothrow) sparc_batch();
     if (!b) return fail(SPARC_E_NOMEM, "host allocation failed");
@@ -420,19 +471,20 @@ int sparc_batch_create(const sparc_batch_job *jobs, int32_t njobs, int32_t mode,
         c.ldp = odd ? j.ldy : op->nd;
         c.ldq = odd ? op->nd : j.ldy;
         c.G = (char *)b->d_work + goff[i];
-        // stencil geometry: 32 x 16 patches, x split so each step has >= ~64 waves per cluster
+        // stencil geometry: 32 x 16 patches; x is split only when a cluster
+        // would have fewer than ~64 stencil items per step
         c.tiles_y = (c.n2 + 15) / 16;
         c.tiles_z = (c.n3 + 31) / 32;
-        const long long per = (long long)c.tiles_y * c.tiles_z * j.ns;
-        int nch = (int)std::max<long long>(1, std::min<long long>((256 + per - 1) / per, c.n1 / 8));
+        const long long per = (long long)c.tiles_y * c.tiles_z * ((j.ns + kBatchColGroup - 1) / kBatchColGroup);
+        int nch = (int)std::max<long long>(1, std::min<long long>((64 + per - 1) / per, c.n1 / 8));
         if (op->tune_chunk[j.dtype] > 0) nch = (c.n1 + op->tune_chunk[j.dtype] - 1) / op->tune_chunk[j.dtype];
         c.chunk_x = (c.n1 + nch - 1) / nch;
         c.nchunks = (c.n1 + c.chunk_x - 1) / c.chunk_x;
-        const long long nS = per * c.nchunks;
         c.ncb = (j.ns + 15) / 16;
         c.ncg = (j.ns + kScatterCols - 1) / kScatterCols;
-        const long long nG = op->natoms > 0 ? (long long)op->natoms * c.ncb * kGatherSplit : 0;
-        const long long nC = op->natoms > 0 ? (long long)op->nl_nblk * c.ncg : 0;
+        const long long nS = (long long)c.tiles_y * c.tiles_z * c.nchunks * ((j.ns + kBatchColGroup - 1) / kBatchColGroup);
+        const long long nG = op->natoms > 0 ? (long long)op->natoms * kGatherSplit : 0;
+        const long long nC = op->natoms > 0 ? (long long)op->nl_nblk : 0;
         if (nS > 0x7fffffffLL || nG > 0x7fffffffLL || nC > 0x7fffffffLL)
             return cleanup(fail(SPARC_E_SHAPE, "job " + std::to_string(i) + ": too many work items"));
         c.nS = (int)nS;
@@ -490,6 +542,7 @@ int sparc_batch_create(const sparc_batch_job *jobs, int32_t njobs, int32_t mode,
     int cus = 0, per_cu = 0;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
     hipError_t oe;
+    if (b->total > 0x7fffffffLL) return cleanup(fail(SPARC_E_SHAPE, "batch has too many work items"));
     if (b->f32 && b->f64)
         oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<true, true>, kBatchNT, 0);
     else if (b->f64)
@@ -517,7 +570,7 @@ int sparc_batch_run(sparc_batch *b, void *stream)
         }
         return SPARC_OK;
     }
-    if (b->mode == 0) {
+    if (b->mode == 0 || b->mode == 4) {
         if (!b->exec) {
             // capture once on the batch's own stream; the graph holds the
             // counter reset (a kernel, no memset node) and the persistent kernel

@@ -53,7 +53,7 @@ __device__ inline int acc_row(int lane, int r)
 constexpr int kGatherUnroll = 8;  // groups of 4 points per wave per batch
 
 template <typename T>
-__device__ void gather_item(const GatherArgs<T> &g, int atom, int cb, int ks, T (*tile)[16][16])
+__device__ __forceinline__ void gather_item(const GatherArgs<T> &g, int atom, int cb, int ks, T (*tile)[16][16])
 {
     const int c0 = cb * 16;
     const AtomDev A = g.atoms[atom];
@@ -129,7 +129,7 @@ struct ScatterArgs {
 };
 
 template <typename T>
-__device__ void scatter_item(const ScatterArgs<T> &s, int b, int cg, T (*gl)[kMaxProj][kScatterCols])
+__device__ __forceinline__ void scatter_item(const ScatterArgs<T> &s, int b, int cg, T (*gl)[kMaxProj][kScatterCols])
 {
     const int c0 = cg * kScatterCols;
     const int a0 = s.blk_at[b];

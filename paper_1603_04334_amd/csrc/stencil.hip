@@ -98,6 +98,7 @@ static int launch_step_t(const sparc_op *op, const void *yk, int64_t ldk, const 
     const long long nb = (long long)ns * a.nchunks * a.tiles_y * a.tiles_z;
     if (nb > 0x7fffffffLL) return fail(SPARC_E_SHAPE, "too many workgroups for one launch");
     a.nblocks = (int)nb;
+    a.remap = 1;
     a.c0 = (T)(-3.0 * op->w[0]);
     for (int p = 1; p <= kMaxRadius; ++p) a.cp[p - 1] = (T)(-0.5 * op->w[p]);
     a.alpha = (T)c.alpha;

@@ -17,6 +17,7 @@ struct StepArgs {
     int n1, n2, n3;
     int tiles_y, tiles_z, nchunks, chunk_x;
     int nblocks;
+    int remap;         // 1: spread consecutive block indices over the XCDs' patch ranges
     T c0;              // centre coefficient of -1/2 lap_h: -3 w_0
     T cp[kMaxRadius];  // -1/2 w_p, p = 1..kMaxRadius (zero beyond the op's radius)
     T alpha, beta, shift;
@@ -137,13 +138,13 @@ struct StepKernel {
     static constexpr size_t kLdsBytes = sizeof(T) * 2 * SY * SZ;
 
     // b: workgroup index within the launch (or work item within a batch)
-    __device__ void run(int b, T (*lds)[SY * SZ])
+    __device__ __forceinline__ void run(int b, T (*lds)[SY * SZ])
     {
         // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
         // contiguous range of patches so that neighbours share its L2.
         const int nb = a.nblocks;
         const int xcd = b & 7;
-        int t = xcd * (nb >> 3) + min(xcd, nb & 7) + (b >> 3);
+        int t = a.remap ? xcd * (nb >> 3) + min(xcd, nb & 7) + (b >> 3) : b;
         const int tzi = t % a.tiles_z;
         t /= a.tiles_z;
         const int tyi = t % a.tiles_y;

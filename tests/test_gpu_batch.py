@@ -42,7 +42,7 @@ def _setup():
     return binding, jobs
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4])
 def test_batch_bitwise_equals_standalone(mode):
     binding, jobs = _setup()
     outs = [torch.full_like(j["Xd"], float("nan")) for j in jobs]
@@ -77,3 +77,22 @@ def test_batch_against_oracle_sampled():
         err = (np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)).max()
         assert err <= tol, (j["cl"].n, err)
     batch.close()
+
+
+def test_autotune_keeps_results_bitwise():
+    from paper_1603_04334_amd import binding
+    binding.lib()
+    cl = inputs.make_cluster((30, 33, 40), 0.45, 3, 8, 1, seed=77, min_dist=0.0, margin=3.0)
+    X = inputs.round_to_f32(inputs.orbitals(cl.nd, 5, seed=77))
+    op = binding.Operator(cl)
+    Xd = torch.from_numpy(X).float().cuda()
+    bounds = (-3.0, 1.5, oracle.upper_bound(cl))
+    ref = op.cheb_filter(Xd, 9, *bounds)
+    tz, ty, cx, us = op.autotune(binding.SPARC_F32, 5)
+    assert us > 0 and (tz, ty) in [(32, 16), (32, 32), (32, 48), (64, 8), (64, 16)] and 1 <= cx <= 30
+    assert op.step_config(binding.SPARC_F32, 5)[2] == cx
+    assert torch.equal(op.cheb_filter(Xd, 9, *bounds), ref)
+    # every explicit configuration gives the same bits
+    for (tz, ty, ch) in [(32, 16, 0), (64, 8, 7), (32, 48, 30), (64, 16, 4)]:
+        op.set_launch(binding.SPARC_F32, tz, ty, ch)
+        assert torch.equal(op.cheb_filter(Xd, 9, *bounds), ref), (tz, ty, ch)
