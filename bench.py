@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 KSTEPS_LANCZOS = 40
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic_cluster96.txt")
-STENCIL_SRC = os.path.join(ROOT, "paper_1603_04334_amd", "csrc", "stencil.hip")
+STENCIL_SRCS = [os.path.join(ROOT, "paper_1603_04334_amd", "csrc", f) for f in ("stencil.hip", "step_kernel.hpp")]
 
 
 def parse():
@@ -41,13 +41,23 @@ def parse():
     p.add_argument("--no-fp64-compare", action="store_true")
     p.add_argument("--no-batch", action="store_true", help="skip the batched uneven-cluster measurement")
     p.add_argument("--batch-only", action="store_true", help="print only the batched measurement")
+    p.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    p.add_argument("--serve-only", action="store_true", help="print only the serving measurement")
+    p.add_argument("--serve-rates", default="100",
+                   help="comma-separated Poisson arrival rates in requests/s (full sweep: 50,100,200,500,1000,2000)")
+    p.add_argument("--serve-requests", type=int, default=500, help="requests per rate point (5 per cluster)")
+    p.add_argument("--serve-workers", type=int, default=4)
     p.add_argument("--copy-calibration", action="store_true",
                    help="run only a plain device copy of known size (for counter calibration)")
     return p.parse_args()
 
 
 def source_hash() -> str:
-    return hashlib.sha256(open(STENCIL_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the step kernel's sources (launch code and kernel body)."""
+    h = hashlib.sha256()
+    for f in STENCIL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic(dtype):
@@ -188,6 +198,117 @@ def batch_measure(reps=5, nclusters=64):
     return out
 
 
+SERVE_STEPS = 5
+SERVE_BUDGET = 250e9
+
+
+class ServeSetup:
+    """Clusters of the serving stream (grid edge log-uniform in [24,128], h =
+    0.45, 1-64 atoms, 8-256 orbitals, degree 20-30, FP32:FP64 = 80:20), built
+    once.  Synthetic orbitals and Lanczos starts are prefixes of one seeded
+    N(0,1) device buffer per dtype, which the server copies at admission."""
+
+    def __init__(self, nclusters):
+        import torch
+        from paper_1603_04334_amd import binding, inputs
+        self.recipe0 = inputs.serving_recipe(seed=5, nclusters=nclusters, rate=1.0, steps_per_cluster=SERVE_STEPS)
+        specs = {}
+        for r in self.recipe0:
+            specs[r["cluster"]["seed"]] = r["cluster"]
+        self.specs = specs
+        maxnd = max(c["n"] ** 3 for c in specs.values())
+        maxns = max(c["ns"] for c in specs.values())
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(5)
+        self.X64 = torch.randn(maxnd * maxns, generator=gen, device="cuda", dtype=torch.float64)
+        self.X32 = self.X64[: maxnd * maxns].float() if any(c["fp32"] for c in specs.values()) else None
+        self.v0 = torch.randn(maxnd, generator=gen, device="cuda", dtype=torch.float64)
+        torch.cuda.synchronize()
+        self.descs = {}
+        self.work = {}
+        for sd, c in specs.items():
+            cl = inputs.make_cluster(c["n"], c["h"], c["natoms"], c["zmax"], c["lmax"], sd)
+            src = self.X32 if c["fp32"] else self.X64
+            X0 = src[: cl.nd * c["ns"]].view(c["ns"], cl.nd)
+            self.descs[sd] = binding.cluster_desc(cl, X0, self.v0[: cl.nd], c["m"])
+            self.work[sd] = cl.nd * c["ns"] * c["m"]
+
+
+def serve_point(setup, rate, nclusters, workers):
+    """Open-loop run: requests are submitted at their Poisson arrival times;
+    latency = completion - scheduled arrival (so a slow client cannot hide
+    queueing)."""
+    from paper_1603_04334_amd import binding, inputs
+    reqs = inputs.serving_recipe(seed=5, nclusters=nclusters, rate=rate, steps_per_cluster=SERVE_STEPS)
+    srv = binding.Server(workers=workers, budget=int(SERVE_BUDGET), lanczos_steps=KSTEPS_LANCZOS)
+    tickets = []
+    refused = []
+    lag = 0.0
+    try:
+        t0 = binding.clock() + 0.01
+        for r in reqs:
+            c = r["cluster"]
+            t_s = t0 + r["t_arrive"]
+            while True:
+                dt = t_s - binding.clock()
+                if dt <= 0:
+                    break
+                time.sleep(dt if dt > 2e-3 else 0)
+            first = r["step"] == 0
+            try:
+                tk = srv.submit(c["seed"], setup.descs[c["seed"]] if first else None,
+                                release=r["step"] == SERVE_STEPS - 1)
+            except binding.SparcError as e:  # the cluster already failed
+                refused.append(e.status)
+                continue
+            lag = max(lag, binding.clock() - t_s)
+            tickets.append((tk, t_s, c["seed"], c["fp32"]))
+        res = {}
+        deadline = time.time() + 900
+        while len(res) < len(tickets):
+            for tk, *_ in tickets:
+                if tk not in res:
+                    r = srv.poll(tk)
+                    if r is not None:
+                        res[tk] = r
+            if time.time() > deadline:
+                raise RuntimeError("serving run did not finish")
+            time.sleep(0.002)
+    finally:
+        srv.close()
+    failed = {}
+    for st in [r["status"] for r in res.values() if r["status"] != 0] + refused:
+        failed[binding.status_name(st)] = failed.get(binding.status_name(st), 0) + 1
+    ok = [(tk, t_s, f) for tk, t_s, _, f in tickets if res[tk]["status"] == 0]
+    lat = np.array([res[tk]["t_end"] - t_s for tk, t_s, _ in ok])
+    lat32 = np.array([res[tk]["t_end"] - t_s for tk, t_s, f in ok if f])
+    lat64 = np.array([res[tk]["t_end"] - t_s for tk, t_s, f in ok if not f])
+    span = max(r["t_end"] for r in res.values()) - t0
+    upd = sum(r["updates"] for r in res.values() if r["status"] == 0)
+    q = lambda a, p: float(np.percentile(a, p) * 1e3) if len(a) else None
+    return {"rate": rate, "requests": len(reqs), "completed": len(ok), "failed": failed, "clusters": nclusters,
+            "p50_ms": q(lat, 50), "p99_ms": q(lat, 99), "mean_ms": float(lat.mean() * 1e3),
+            "p50_ms_f32": q(lat32, 50), "p99_ms_f32": q(lat32, 99), "p50_ms_f64": q(lat64, 50),
+            "p99_ms_f64": q(lat64, 99), "throughput_req_s": len(ok) / span, "updates_per_s": upd / span,
+            "span_s": span, "max_submit_lag_ms": lag * 1e3}
+
+
+def serve_measure(rates, nrequests, workers):
+    import torch
+    nclusters = max(1, nrequests // SERVE_STEPS)
+    setup = ServeSetup(nclusters)
+    # warm-up: kernels, rocBLAS/rocSOLVER handles, allocator pools
+    serve_point(setup, 1e6, min(nclusters, 8), workers)
+    points = [serve_point(setup, r, nclusters, workers) for r in rates]
+    out = {"workload": f"{nclusters} clusters x {SERVE_STEPS} filtered-subspace passes (Lanczos bounds on the "
+                       f"first), grid edge log-uniform 24-128, h=0.45, 1-64 atoms, 8-256 orbitals, degree 20-30, "
+                       f"FP32:FP64 = 80:20, Poisson arrivals, open loop",
+           "workers": workers, "budget_bytes": SERVE_BUDGET, "points": points}
+    del setup
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(case, cl):
     import oracle
     from paper_1603_04334_amd import inputs
@@ -217,6 +338,10 @@ def main():
     binding.lib()
     if args.batch_only:
         print(json.dumps(batch_measure()), flush=True)
+        return
+    rates = [float(r) for r in args.serve_rates.split(",") if r]
+    if args.serve_only:
+        print(json.dumps(serve_measure(rates, args.serve_requests, args.serve_workers)), flush=True)
         return
     case = inputs.MEDIUM
     cl = inputs.case_cluster(case.name)
@@ -285,6 +410,9 @@ def main():
     if not args.no_batch:
         torch.cuda.empty_cache()
         out["batched"] = batch_measure()
+    if not args.no_serve:
+        torch.cuda.empty_cache()
+        out["serving"] = serve_measure(rates, args.serve_requests, args.serve_workers)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, cl)
     print(json.dumps(out), flush=True)

@@ -51,11 +51,11 @@ typedef enum {
     SPARC_E_BOUNDS = -3,     /* filter bounds not a0 < a < b, or m < 1           */
     SPARC_E_NOMEM = -4,      /* device allocation failed / budget exceeded       */
     SPARC_E_HIP = -5,        /* a HIP runtime or library call failed             */
-    SPARC_E_BUSY = -6,       /* server queue full                                */
+    SPARC_E_BUSY = -6,       /* reserved                                         */
     SPARC_E_TICKET = -7,     /* unknown ticket                                   */
     SPARC_E_JOB = -8,        /* job failed (see sparc_job_result.status)         */
     SPARC_E_WORKSPACE = -9,  /* workspace missing or too small                   */
-    SPARC_E_BREAKDOWN = -10, /* Lanczos reached an invariant subspace            */
+    SPARC_E_BREAKDOWN = -10, /* Lanczos invariant subspace / singular M_s        */
     SPARC_E_ALIAS = -11      /* input and output / workspace overlap             */
 } sparc_status;
 
@@ -178,8 +178,9 @@ size_t sparc_rr_workspace_bytes(const sparc_op *op, int32_t dtype, int32_t ns);
  * theta: host array of ns Ritz values, ascending.  evec: optional device FP64
  * ns x ns column-major array receiving the M_s-orthonormal eigenvectors (the
  * rotation matrix of Eq. OrbitalTransformation).  Synchronous.
- * Errors: SPARC_E_ARG, SPARC_E_SHAPE, SPARC_E_WORKSPACE, SPARC_E_HIP
- * (including a singular M_s reported by the eigensolver). */
+ * Errors: SPARC_E_ARG, SPARC_E_SHAPE, SPARC_E_WORKSPACE, SPARC_E_HIP,
+ * SPARC_E_BREAKDOWN (M_s not numerically positive definite: the filtered
+ * columns are linearly dependent to working precision). */
 int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_t ldy, int32_t ns,
                         double *theta, double *evec, void *ws, size_t ws_bytes, void *stream);
 
@@ -239,6 +240,104 @@ int sparc_batch_info(const sparc_batch *batch, int64_t *items, int32_t *levels, 
 
 /* Free the batch (its graph, schedule and workspaces).  NULL is accepted. */
 int sparc_batch_destroy(sparc_batch *batch);
+
+/* ------------------------------------------------------------------ serving */
+
+/* Server configuration: device memory budget for resident clusters (0 = 250 GB),
+ * number of worker threads (requests on the device at once, each on its own
+ * stream; 1..64) and Lanczos steps for the bounds (0 = 40). */
+typedef struct {
+    uint64_t hbm_budget_bytes;
+    int32_t workers;
+    int32_t lanczos_steps;
+} sparc_server_cfg;
+
+/* A cluster: the operator (as for sparc_op_create), dtype, orbital count ns
+ * and filter degree m, its initial orbitals X0 (device block of dtype, ns
+ * columns, leading dimension ldx0) and the device FP64 Lanczos start v0 (N_d
+ * values).  Host arrays are copied at submission; X0 and v0 must be complete
+ * (their producing work finished) when the first request is submitted, are
+ * read when the cluster is admitted and must stay valid until that request is
+ * done.  The server copies X0, so the caller's block is never written. */
+typedef struct {
+    sparc_grid grid;
+    const double *veff;
+    int32_t natoms;
+    const sparc_atom *atoms;
+    int32_t dtype;
+    int32_t ns;
+    int32_t m;
+    const void *X0;
+    int64_t ldx0;
+    const double *v0;
+} sparc_cluster_desc;
+
+/* One request: a filtered-subspace pass (Sec. 3.4: Chebyshev filter, FP64
+ * Rayleigh-Ritz, rotation) on the resident orbitals of cluster `cluster` (an
+ * id chosen by the caller).  The first request of a cluster carries its
+ * description; it builds the operator, copies X0 and computes the filter
+ * bounds with the device Lanczos (a = theta_8 + 0.1, b = 1.01 theta_max capped
+ * by the upper bound), which the cluster's later requests reuse.  The rotated
+ * orbitals stay resident for the next request.  The first pass of an FP32
+ * cluster runs in FP64 from the caller's block (a filter applied to an
+ * unconverged block concentrates every column on the lowest eigenvectors,
+ * beyond what FP32 resolves) and stores the rotated orbitals rounded to FP32;
+ * later passes run in FP32.  release = 1 frees the
+ * cluster's device memory after this request.  ritz: optional host buffer of
+ * ns doubles receiving the Ritz values; it must stay valid until the request
+ * is done. */
+typedef struct {
+    uint64_t cluster;
+    const sparc_cluster_desc *desc;
+    int32_t release;
+    double *ritz;
+} sparc_filter_job;
+
+/* Outcome of a request: status (SPARC_OK or the failing call's code;
+ * SPARC_E_JOB when an earlier request of the cluster failed), 0-based index of
+ * the request within its cluster, steady-clock times (seconds, as
+ * sparc_clock) of submission, start and completion, lowest Ritz value, and
+ * N_d * ns * m filtered orbital*gridpoint updates. */
+typedef struct {
+    int32_t status;
+    int32_t step;
+    double t_submit, t_start, t_end;
+    double lambda_min;
+    int64_t updates;
+} sparc_job_result;
+
+typedef struct sparc_server sparc_server;
+
+/* Start a server on the current device with cfg->workers worker threads. */
+int sparc_server_create(const sparc_server_cfg *cfg, sparc_server **out);
+
+/* Queue a request; returns at once with a ticket.  A cluster is admitted when
+ * its estimated device footprint fits the budget beside the resident
+ * clusters; requests of one cluster run in submission order; requests of
+ * different clusters run concurrently (continuous batching).
+ * Errors: SPARC_E_ARG (bad or duplicate description, unknown cluster),
+ * SPARC_E_BOUNDS, SPARC_E_SHAPE, SPARC_E_NOMEM (footprint above the whole
+ * budget), SPARC_E_JOB (cluster already released or failed). */
+int sparc_filter_submit(sparc_server *srv, const sparc_filter_job *job, uint64_t *ticket);
+
+/* SPARC_OK with the result when the request is done (the ticket is then
+ * retired), SPARC_PENDING while it waits or runs, SPARC_E_TICKET for an
+ * unknown or retired ticket. */
+int sparc_filter_poll(sparc_server *srv, uint64_t ticket, sparc_job_result *result);
+
+/* Counts of finished (not yet polled or polled), pending and running requests,
+ * and the reserved device bytes. */
+int sparc_server_stats(sparc_server *srv, int64_t *done, int64_t *pending, int64_t *running, uint64_t *hbm_used);
+
+/* Finish running requests, drop pending ones, free every cluster, stop the workers. */
+int sparc_server_destroy(sparc_server *srv);
+
+/* Seconds on the steady clock used for request times. */
+double sparc_clock(void);
+
+/* Device bytes the server reserves for a cluster when admitting it (operator,
+ * resident orbitals, filter, Rayleigh-Ritz and Lanczos workspaces).  Host only. */
+uint64_t sparc_cluster_footprint(const sparc_cluster_desc *desc, int32_t lanczos_steps);
 
 /* ------------------------------------------------------------- diagnostics */
 

@@ -27,6 +27,13 @@ SPARC_OK, SPARC_PENDING = 0, 1
 SPARC_E_ARG, SPARC_E_SHAPE, SPARC_E_BOUNDS, SPARC_E_NOMEM, SPARC_E_HIP = -1, -2, -3, -4, -5
 SPARC_E_BUSY, SPARC_E_TICKET, SPARC_E_JOB, SPARC_E_WORKSPACE, SPARC_E_BREAKDOWN, SPARC_E_ALIAS = -6, -7, -8, -9, -10, -11
 SPARC_F64, SPARC_F32 = 0, 1
+_STATUS_NAMES = {0: "SPARC_OK", 1: "SPARC_PENDING", -1: "SPARC_E_ARG", -2: "SPARC_E_SHAPE", -3: "SPARC_E_BOUNDS",
+                 -4: "SPARC_E_NOMEM", -5: "SPARC_E_HIP", -6: "SPARC_E_BUSY", -7: "SPARC_E_TICKET", -8: "SPARC_E_JOB",
+                 -9: "SPARC_E_WORKSPACE", -10: "SPARC_E_BREAKDOWN", -11: "SPARC_E_ALIAS"}
+
+
+def status_name(status: int) -> str:
+    return _STATUS_NAMES.get(int(status), f"status {status}")
 
 
 class SparcError(RuntimeError):
@@ -48,6 +55,27 @@ class sparc_batch_job(ctypes.Structure):
     _fields_ = [("op", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("X", ctypes.c_void_p), ("ldx", ctypes.c_int64),
                 ("Y", ctypes.c_void_p), ("ldy", ctypes.c_int64), ("ns", ctypes.c_int32), ("m", ctypes.c_int32),
                 ("a0", ctypes.c_double), ("a", ctypes.c_double), ("b", ctypes.c_double)]
+
+
+class sparc_server_cfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("workers", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32)]
+
+
+class sparc_cluster_desc(ctypes.Structure):
+    _fields_ = [("grid", sparc_grid), ("veff", ctypes.POINTER(ctypes.c_double)), ("natoms", ctypes.c_int32),
+                ("atoms", ctypes.POINTER(sparc_atom)), ("dtype", ctypes.c_int32), ("ns", ctypes.c_int32),
+                ("m", ctypes.c_int32), ("X0", ctypes.c_void_p), ("ldx0", ctypes.c_int64), ("v0", ctypes.c_void_p)]
+
+
+class sparc_filter_job(ctypes.Structure):
+    _fields_ = [("cluster", ctypes.c_uint64), ("desc", ctypes.POINTER(sparc_cluster_desc)), ("release", ctypes.c_int32),
+                ("ritz", ctypes.POINTER(ctypes.c_double))]
+
+
+class sparc_job_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("step", ctypes.c_int32), ("t_submit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_end", ctypes.c_double), ("lambda_min", ctypes.c_double),
+                ("updates", ctypes.c_int64)]
 
 
 _lib = None
@@ -81,6 +109,14 @@ _SIGS = {
     "sparc_op_set_launch": (_i32, [_vp, _i32, _i32, _i32, _i32]),
     "sparc_autotune": (_i32, [_vp, _i32, _i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                               _dp]),
+    "sparc_server_create": (_i32, [ctypes.POINTER(sparc_server_cfg), ctypes.POINTER(_vp)]),
+    "sparc_filter_submit": (_i32, [_vp, ctypes.POINTER(sparc_filter_job), ctypes.POINTER(ctypes.c_uint64)]),
+    "sparc_filter_poll": (_i32, [_vp, ctypes.c_uint64, ctypes.POINTER(sparc_job_result)]),
+    "sparc_server_stats": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                                  ctypes.POINTER(ctypes.c_uint64)]),
+    "sparc_server_destroy": (_i32, [_vp]),
+    "sparc_clock": (ctypes.c_double, []),
+    "sparc_cluster_footprint": (ctypes.c_uint64, [ctypes.POINTER(sparc_cluster_desc), _i32]),
     "sparc_batch_create": (_i32, [ctypes.POINTER(sparc_batch_job), _i32, _i32, ctypes.POINTER(_vp)]),
     "sparc_batch_run": (_i32, [_vp, _vp]),
     "sparc_batch_check": (_i32, [_vp, _vp, ctypes.POINTER(_i32)]),
@@ -167,26 +203,10 @@ class Operator:
 
     def __init__(self, cluster):
         self.cluster = cluster
-        g = sparc_grid()
-        g.n[:] = list(cluster.n)
-        g.h = cluster.h
-        g.radius = cluster.radius
-        self._keep = []
-        atoms = (sparc_atom * max(1, len(cluster.atoms)))()
-        for i, a in enumerate(cluster.atoms):
-            chi = np.ascontiguousarray(a.chi, dtype=np.float64).reshape(-1)
-            gam = np.ascontiguousarray(a.gamma, dtype=np.float64)
-            self._keep += [chi, gam]
-            atoms[i].lo[:] = list(a.lo)
-            atoms[i].ext[:] = list(a.ext)
-            atoms[i].nproj = a.chi.shape[0]
-            atoms[i].chi = chi.ctypes.data_as(_dp)
-            atoms[i].gamma = gam.ctypes.data_as(_dp)
-        veff = np.ascontiguousarray(cluster.veff, dtype=np.float64)
+        g, atoms, veff, keep = _cluster_arrays(cluster)
         h = _vp()
         check(lib().sparc_op_create(ctypes.byref(g), veff.ctypes.data_as(_dp), len(cluster.atoms), atoms,
                                     ctypes.byref(h)), "sparc_op_create")
-        self._keep = []
         self.handle = h
         self.nd = int(lib().sparc_op_nd(h))
 
@@ -353,6 +373,106 @@ class Batch:
         if getattr(self, "handle", None):
             lib().sparc_batch_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _cluster_arrays(cluster):
+    """ctypes grid, atom array and the host buffers they point to."""
+    g = sparc_grid()
+    g.n[:] = list(cluster.n)
+    g.h = cluster.h
+    g.radius = cluster.radius
+    keep = []
+    atoms = (sparc_atom * max(1, len(cluster.atoms)))()
+    for i, a in enumerate(cluster.atoms):
+        chi = np.ascontiguousarray(a.chi, dtype=np.float64).reshape(-1)
+        gam = np.ascontiguousarray(a.gamma, dtype=np.float64)
+        keep += [chi, gam]
+        atoms[i].lo[:] = list(a.lo)
+        atoms[i].ext[:] = list(a.ext)
+        atoms[i].nproj = a.chi.shape[0]
+        atoms[i].chi = chi.ctypes.data_as(_dp)
+        atoms[i].gamma = gam.ctypes.data_as(_dp)
+    veff = np.ascontiguousarray(cluster.veff, dtype=np.float64)
+    keep.append(veff)
+    return g, atoms, veff, keep
+
+
+def cluster_desc(cluster, X0, v0, m: int):
+    """sparc_cluster_desc for an inputs.Cluster with device tensors X0 (ns, ld) and v0 (N_d, float64)."""
+    g, atoms, veff, keep = _cluster_arrays(cluster)
+    ns, ld = _block(X0, cluster.nd, "X0")
+    d = sparc_cluster_desc()
+    d.grid = g
+    d.veff = veff.ctypes.data_as(_dp)
+    d.natoms = len(cluster.atoms)
+    d.atoms = atoms
+    d.dtype = _dtype_code(X0)
+    d.ns = ns
+    d.m = int(m)
+    d.X0 = _ptr(X0)
+    d.ldx0 = ld
+    d.v0 = _ptr(v0)
+    return d, keep + [atoms, X0, v0]
+
+
+def cluster_footprint(cluster, X0, v0, m: int, lanczos_steps: int = 0) -> int:
+    d, keep = cluster_desc(cluster, X0, v0, m)
+    return int(lib().sparc_cluster_footprint(ctypes.byref(d), int(lanczos_steps)))
+
+
+def clock() -> float:
+    return float(lib().sparc_clock())
+
+
+class Server:
+    """Request server: one filtered-subspace pass per request on resident clusters."""
+
+    def __init__(self, workers: int = 4, budget: int = 0, lanczos_steps: int = 0):
+        cfg = sparc_server_cfg(int(budget), int(workers), int(lanczos_steps))
+        h = _vp()
+        check(lib().sparc_server_create(ctypes.byref(cfg), ctypes.byref(h)), "sparc_server_create")
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, cluster_id: int, desc=None, release: bool = False, ritz=None) -> int:
+        """desc: (sparc_cluster_desc, keep) from cluster_desc() for the cluster's first request."""
+        job = sparc_filter_job()
+        job.cluster = int(cluster_id)
+        if desc is not None:
+            job.desc = ctypes.pointer(desc[0])
+            self._keep[int(cluster_id)] = desc[1]  # X0 and v0 must outlive admission
+        job.release = 1 if release else 0
+        if ritz is not None:
+            job.ritz = ritz.ctypes.data_as(_dp)
+        t = ctypes.c_uint64()
+        check(lib().sparc_filter_submit(self.handle, ctypes.byref(job), ctypes.byref(t)), "sparc_filter_submit")
+        return t.value
+
+    def poll(self, ticket: int):
+        r = sparc_job_result()
+        st = lib().sparc_filter_poll(self.handle, ctypes.c_uint64(ticket), ctypes.byref(r))
+        if st == SPARC_PENDING:
+            return None
+        check(st, "sparc_filter_poll")
+        return {"status": r.status, "step": r.step, "t_submit": r.t_submit, "t_start": r.t_start, "t_end": r.t_end,
+                "lambda_min": r.lambda_min, "updates": r.updates}
+
+    def stats(self):
+        d, p, r, u = _i64(), _i64(), _i64(), ctypes.c_uint64()
+        check(lib().sparc_server_stats(self.handle, ctypes.byref(d), ctypes.byref(p), ctypes.byref(r), ctypes.byref(u)))
+        return {"done": d.value, "pending": p.value, "running": r.value, "hbm_used": u.value}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().sparc_server_destroy(self.handle)
+            self.handle = None
+            self._keep = {}
 
     def __del__(self):
         try:

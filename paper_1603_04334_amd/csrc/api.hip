@@ -124,11 +124,11 @@ const char *sparc_status_str(int s)
         case SPARC_E_BOUNDS: return "invalid filter bounds or degree";
         case SPARC_E_NOMEM: return "out of device memory";
         case SPARC_E_HIP: return "HIP runtime error";
-        case SPARC_E_BUSY: return "server busy";
+        case SPARC_E_BUSY: return "reserved";
         case SPARC_E_TICKET: return "unknown ticket";
         case SPARC_E_JOB: return "job failed";
         case SPARC_E_WORKSPACE: return "workspace missing or too small";
-        case SPARC_E_BREAKDOWN: return "Lanczos breakdown";
+        case SPARC_E_BREAKDOWN: return "numerical breakdown (Lanczos invariant subspace or singular M_s)";
         case SPARC_E_ALIAS: return "overlapping buffers";
     }
     return "unknown status";

@@ -7,9 +7,14 @@
 //   2. reduction to standard form C = L^{-1} H_s L^{-T} by two triangular
 //      solves (one thread per column);
 //   3. cyclic Jacobi on C with the round-robin (circle) ordering, so the n/2
-//      rotations of a round touch disjoint rows/columns and are applied in
-//      parallel; sweeps stop when the off-diagonal mass is below 1e-30 of the
-//      total (relative 1e-15 in norm) or after max_sweeps;
+//      rotations of a round touch disjoint rows/columns.  A round is applied
+//      as one two-sided update: one wave computes the round's rotations, and
+//      the thread owning row pair k and column pair l maps the 2 x 2 block of
+//      C at (rows of k, columns of l) through the row rotation of k and then
+//      the column rotation of l, reading C from one LDS buffer and writing
+//      the other (two barriers per round, C read and written once).
+//      Sweeps stop when the off-diagonal mass is below 1e-30 of the total
+//      (relative 1e-15 in norm) or after max_sweeps;
 //   4. eigenvalues sorted ascending (stable), eigenvectors back-transformed
 //      q = L^{-T} z so that Q^T M_s Q = I.
 // Rotation for the pair (p, q): tau = (c_qq - c_pp) / (2 c_pq),
@@ -34,27 +39,61 @@ __device__ inline double block_sum_eig(double v, double *red)
     return t;
 }
 
+// Jacobi rotation (c, s) annihilating C[p][q], for a pair of the round;
+// the identity for the padding pair of an odd n
+__device__ inline void jacobi_params(const double (*C)[kEigMax + 1], int p, int q, int n, double &c, double &s)
+{
+    c = 1.0;
+    s = 0.0;
+    if (q < n && C[p][q] != 0.0) {
+        const double tau = (C[q][q] - C[p][p]) / (2.0 * C[p][q]);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        c = 1.0 / sqrt(1.0 + t * t);
+        s = t * c;
+    }
+}
+
+// indices (p < q) of pair k in round r of the circle ordering over np indices
+__device__ inline void round_pair(int np, int r, int k, int &p, int &q)
+{
+    if (k == 0) {
+        p = np - 1;
+        q = r;
+    } else {
+        p = (r + k) % (np - 1);
+        q = (r - k + np - 1) % (np - 1);
+    }
+    if (p > q) {
+        const int t = p;
+        p = q;
+        q = t;
+    }
+}
+
 __global__ void __launch_bounds__(kEigThreads) small_sygv_kernel(const double *__restrict__ Hs,
                                                                   const double *__restrict__ Ms, int n,
                                                                   double *theta, double *evec, int *info,
                                                                   int max_sweeps)
 {
-    __shared__ double C[kEigMax][kEigMax + 1];
+    __shared__ double CB[2][kEigMax][kEigMax + 1];  // C, double-buffered across Jacobi rounds
     __shared__ double Z[kEigMax][kEigMax + 1];
     __shared__ double L[kEigMax][kEigMax + 1];
-    __shared__ double rc[kEigMax / 2], rs[kEigMax / 2];
-    __shared__ int rp[kEigMax / 2], rq[kEigMax / 2];
     __shared__ double red[kEigThreads / 64];
     __shared__ double lam[kEigMax];
+    __shared__ double rc[kEigMax / 2], rs[kEigMax / 2];
+    __shared__ int rp[kEigMax / 2], rq[kEigMax / 2];
     __shared__ int rank[kEigMax];
     __shared__ int bad;
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
+    const int np = n + (n & 1);
+    double (*C)[kEigMax + 1] = CB[0];
 
-    for (int e = tid; e < n * n; e += nt) {
-        const int i = e % n, j = e / n;  // column-major input
-        L[i][j] = Ms[(long long)j * n + i];
-        C[i][j] = Hs[(long long)j * n + i];
+    for (int e = tid; e < np * np; e += nt) {
+        const int i = e % np, j = e / np;  // column-major input, zero padding row/column for odd n
+        const bool in = i < n && j < n;
+        L[i][j] = in ? Ms[(long long)j * n + i] : 0.0;
+        C[i][j] = in ? Hs[(long long)j * n + i] : 0.0;
     }
     if (tid == 0) bad = 0;
     __syncthreads();
@@ -107,20 +146,21 @@ __global__ void __launch_bounds__(kEigThreads) small_sygv_kernel(const double *_
         C[i][j] = 0.5 * (Z[i][j] + Z[j][i]);
     }
     __syncthreads();
-    for (int e = tid; e < n * n; e += nt) {
+    for (int e = tid; e < n * np; e += nt) {
         const int i = e % n, j = e / n;
         Z[i][j] = i == j ? 1.0 : 0.0;
     }
     __syncthreads();
 
-    // 3. cyclic Jacobi, round-robin pairs over an even number of indices
-    const int np = n + (n & 1);
+    // 3. cyclic Jacobi, one barrier per round
     const int half = np / 2;
+    int cur = 0;
     for (int sweep = 0; sweep < max_sweeps && n > 1; ++sweep) {
+        const double(*A)[kEigMax + 1] = CB[cur];
         double off = 0.0, tot = 0.0;
         for (int e = tid; e < n * n; e += nt) {
             const int i = e % n, j = e / n;
-            const double v = C[i][j] * C[i][j];
+            const double v = A[i][j] * A[i][j];
             tot += v;
             if (i != j) off += v;
         }
@@ -128,64 +168,47 @@ __global__ void __launch_bounds__(kEigThreads) small_sygv_kernel(const double *_
         tot = block_sum_eig(tot, red);
         if (!(off > 1e-30 * tot)) break;
         for (int r = 0; r < np - 1; ++r) {
+            const double(*S)[kEigMax + 1] = CB[cur];
+            double(*D)[kEigMax + 1] = CB[cur ^ 1];
             if (tid < half) {
-                const int k = tid;
                 int p, q;
-                if (k == 0) {
-                    p = np - 1;
-                    q = r;
-                } else {
-                    p = (r + k) % (np - 1);
-                    q = (r - k + np - 1) % (np - 1);
-                }
-                if (p > q) {
-                    const int t = p;
-                    p = q;
-                    q = t;
-                }
-                double c = 1.0, s = 0.0;
-                const bool valid = q < n;
-                if (valid && C[p][q] != 0.0) {
-                    const double tau = (C[q][q] - C[p][p]) / (2.0 * C[p][q]);
-                    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                    c = 1.0 / sqrt(1.0 + t * t);
-                    s = t * c;
-                }
-                rc[k] = c;
-                rs[k] = s;
-                rp[k] = valid ? p : -1;
-                rq[k] = q;
+                round_pair(np, r, tid, p, q);
+                double c, s;
+                jacobi_params(S, p, q, n, c, s);
+                rp[tid] = p;
+                rq[tid] = q;
+                rc[tid] = c;
+                rs[tid] = s;
             }
             __syncthreads();
-            for (int e = tid; e < half * n; e += nt) {
-                const int k = e / n, j = e % n;
-                const int p = rp[k];
-                if (p < 0) continue;
-                const int q = rq[k];
-                const double c = rc[k], s = rs[k];
-                const double a = C[p][j], b = C[q][j];
-                C[p][j] = c * a - s * b;
-                C[q][j] = s * a + c * b;
+            for (int e = tid; e < half * half; e += nt) {
+                const int k = e / half, l = e % half;
+                const int pk = rp[k], qk = rq[k], pl = rp[l], ql = rq[l];
+                const double ck = rc[k], sk = rs[k], cl = rc[l], sl = rs[l];
+                const double a = S[pk][pl], b = S[pk][ql], d = S[qk][pl], g = S[qk][ql];
+                const double a1 = ck * a - sk * d, b1 = ck * b - sk * g;
+                const double d1 = sk * a + ck * d, g1 = sk * b + ck * g;
+                D[pk][pl] = cl * a1 - sl * b1;
+                D[pk][ql] = sl * a1 + cl * b1;
+                D[qk][pl] = cl * d1 - sl * g1;
+                D[qk][ql] = sl * d1 + cl * g1;
             }
-            __syncthreads();
             for (int e = tid; e < half * n; e += nt) {
-                const int k = e / n, i = e % n;
-                const int p = rp[k];
-                if (p < 0) continue;
-                const int q = rq[k];
-                const double c = rc[k], s = rs[k];
-                const double a = C[i][p], b = C[i][q];
-                C[i][p] = c * a - s * b;
-                C[i][q] = s * a + c * b;
-                const double za = Z[i][p], zb = Z[i][q];
-                Z[i][p] = c * za - s * zb;
-                Z[i][q] = s * za + c * zb;
+                const int l = e / n, i = e % n;
+                const int pl = rp[l], ql = rq[l];
+                const double cl = rc[l], sl = rs[l];
+                const double za = Z[i][pl], zb = Z[i][ql];
+                Z[i][pl] = cl * za - sl * zb;
+                Z[i][ql] = sl * za + cl * zb;
             }
+            cur ^= 1;
             __syncthreads();
         }
     }
+    C = CB[cur];
 
-    // 4. sort (stable ascending) and back-transform q = L^{-T} z
+    // 4. sort (stable ascending) and back-transform q = L^{-T} z (into the other buffer)
+    double(*Q)[kEigMax + 1] = CB[cur ^ 1];
     if (tid < n) lam[tid] = C[tid][tid];
     __syncthreads();
     if (tid < n) {
@@ -200,14 +223,14 @@ __global__ void __launch_bounds__(kEigThreads) small_sygv_kernel(const double *_
         const int c = tid;
         for (int k = n - 1; k >= 0; --k) {
             double s = Z[k][c];
-            for (int m = k + 1; m < n; ++m) s -= L[m][k] * C[m][c];
-            C[k][c] = s / L[k][k];
+            for (int m = k + 1; m < n; ++m) s -= L[m][k] * Q[m][c];
+            Q[k][c] = s / L[k][k];
         }
     }
     __syncthreads();
     for (int e = tid; e < n * n; e += nt) {
         const int k = e % n, c = e / n;
-        evec[(long long)rank[c] * n + k] = C[k][c];
+        evec[(long long)rank[c] * n + k] = Q[k][c];
     }
     if (tid == 0) info[0] = 0;
 }

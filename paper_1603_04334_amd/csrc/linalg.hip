@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -273,22 +274,65 @@ static dim3 stream_grid(long long n)
 
 // ---------------------------------------------------------------- BLAS handles
 
+// rocBLAS handles are not safe for concurrent use, and a handle's device
+// workspace stays in use until the work enqueued with it has run.  Each call
+// leases a handle from a per-device pool: one last used on the same stream
+// (stream order protects its workspace) or one whose completion event has
+// fired; otherwise a new handle is made.  Returning a lease records the event
+// on the call's stream.  Handles are kept until the process ends.
 namespace {
-std::mutex g_blas_mu;
-std::map<int, rocblas_handle> g_blas;  // one handle per device
-}  // namespace
-
-static rocblas_handle blas_handle()
-{
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    auto it = g_blas.find(dev);
-    if (it != g_blas.end()) return it->second;
+struct PooledBlas {
     rocblas_handle h = nullptr;
-    if (rocblas_create_handle(&h) != rocblas_status_success) return nullptr;
-    g_blas[dev] = h;
-    return h;
-}
+    hipEvent_t done = nullptr;
+    hipStream_t last = nullptr;
+};
+std::mutex g_blas_mu;
+std::map<int, std::vector<PooledBlas>> g_blas_free;
+
+struct BlasLease {
+    int dev = 0;
+    hipStream_t stream;
+    PooledBlas e;
+    rocblas_handle h = nullptr;
+    explicit BlasLease(hipStream_t s) : stream(s)
+    {
+        (void)hipGetDevice(&dev);
+        bool found = false;
+        {
+            std::lock_guard<std::mutex> lk(g_blas_mu);
+            auto &v = g_blas_free[dev];
+            for (size_t i = 0; i < v.size(); ++i)
+                if (v[i].last == s || hipEventQuery(v[i].done) == hipSuccess) {
+                    e = v[i];
+                    v.erase(v.begin() + (long)i);
+                    found = true;
+                    break;
+                }
+        }
+        if (!found) {
+            if (rocblas_create_handle(&e.h) != rocblas_status_success) return;
+            if (hipEventCreateWithFlags(&e.done, hipEventDisableTiming) != hipSuccess) {
+                rocblas_destroy_handle(e.h);
+                return;
+            }
+            // no atomics: GEMM results must not depend on scheduling
+            rocblas_set_atomics_mode(e.h, rocblas_atomics_not_allowed);
+        }
+        rocblas_set_stream(e.h, s);
+        h = e.h;
+    }
+    ~BlasLease()
+    {
+        if (!h) return;
+        (void)hipEventRecord(e.done, stream);
+        e.last = stream;
+        std::lock_guard<std::mutex> lk(g_blas_mu);
+        g_blas_free[dev].push_back(e);
+    }
+    BlasLease(const BlasLease &) = delete;
+    BlasLease &operator=(const BlasLease &) = delete;
+};
+}  // namespace
 
 // ---------------------------------------------------------------- tridiagonal eigenvalues
 
@@ -492,10 +536,9 @@ int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_
         // one-workgroup Cholesky + Jacobi; eigenvectors land in Hs
         if ((st = launch_small_sygv(Hs, Ms, ns, D, Hs, info, s))) return st;
     } else {
-        std::lock_guard<std::mutex> lk(g_blas_mu);
-        rocblas_handle hb = blas_handle();
+        BlasLease lease(s);
+        rocblas_handle hb = lease.h;
         if (!hb) return fail(SPARC_E_HIP, "rocblas_create_handle failed");
-        rocblas_set_stream(hb, s);
         if (rocsolver_dsygvd(hb, rocblas_eform_ax, evec ? rocblas_evect_original : rocblas_evect_none,
                              rocblas_fill_upper, ns, Hs, ns, Ms, ns, D, E, info) != rocblas_status_success)
             return fail(SPARC_E_HIP, "rocsolver_dsygvd failed");
@@ -505,7 +548,9 @@ int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_
     SPARC_HIP(hipMemcpyAsync(&hinfo, info, sizeof(int), hipMemcpyDeviceToHost, s));
     if (evec) SPARC_HIP(hipMemcpyAsync(evec, Hs, (size_t)ns * ns * sizeof(double), hipMemcpyDeviceToDevice, s));
     SPARC_HIP(hipStreamSynchronize(s));
-    if (hinfo != 0) return fail(SPARC_E_HIP, "generalized eigensolver failed (info=" + std::to_string(hinfo) + ")");
+    if (hinfo != 0)
+        return fail(SPARC_E_BREAKDOWN, "generalized eigensolver failed (info=" + std::to_string(hinfo) +
+                                           "): the filtered block is numerically rank deficient");
     return SPARC_OK;
 }
 
@@ -521,10 +566,9 @@ int sparc_rotate(int32_t dtype, const void *Y, int64_t ldy, int64_t nd, int32_t 
     const char *pa = (const char *)Y, *pb = (const char *)out;
     if (pa < pb + bo && pb < pa + by) return fail(SPARC_E_ALIAS, "Y and out overlap");
     hipStream_t s = (hipStream_t)stream;
-    std::lock_guard<std::mutex> lk(g_blas_mu);
-    rocblas_handle hb = blas_handle();
+    BlasLease lease(s);
+    rocblas_handle hb = lease.h;
     if (!hb) return fail(SPARC_E_HIP, "rocblas_create_handle failed");
-    rocblas_set_stream(hb, s);
     if (dtype == SPARC_F64) {
         const double one = 1.0, zero = 0.0;
         if (rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, (int)nd, ns, ns, &one, (const double *)Y,

@@ -275,10 +275,12 @@ def serving_recipe(seed: int = 5, nclusters: int = 64, rate: float = 200.0,
                    steps_per_cluster: int = 5, edge_range=(24, 128), ns_range=(8, 256),
                    fp32_share: float = 0.8) -> List[dict]:
     """Serving stream: clusters with grid edge log-uniform in [24,128] (rounded to
-    a multiple of 8), h = 0.45, atoms clamp(round(64 (n/128)^3), 1, 64),
-    orbitals U{8..256}, degree U{20..30}, FP32 with probability 0.8, each
-    submitted as ``steps_per_cluster`` consecutive requests; inter-arrival times
-    are exponential with the given rate (requests per second)."""
+    a multiple of 8), h = 0.45, atoms clamp(round(64 (n/128)^3), 1, 64), degree
+    U{20..30}, FP32 with probability 0.8, each submitted as ``steps_per_cluster``
+    consecutive requests; inter-arrival times are exponential with the given
+    rate (requests per second).  The orbital count follows the paper's rule
+    (Sec. 4) N_s = N_e/2 + 30 with N_e = sum of the cluster's Z (the same Z that
+    ``make_cluster`` draws), clamped to ``ns_range``."""
     rng = _rng(seed, _KEY_MISC, 1)
     reqs = []
     t = 0.0
@@ -287,10 +289,12 @@ def serving_recipe(seed: int = 5, nclusters: int = 64, rate: float = 200.0,
         e = math.exp(rng.uniform(math.log(edge_range[0]), math.log(edge_range[1])))
         n = int(max(edge_range[0], min(edge_range[1], 8 * round(e / 8))))
         natoms = int(min(64, max(1, round(64 * (n / 128.0) ** 3))))
-        clusters.append(dict(n=n, h=0.45, natoms=natoms, zmax=8, lmax=1,
-                             ns=int(rng.integers(ns_range[0], ns_range[1] + 1)),
+        cseed = 100000 + 1000 * seed + i
+        ne = int(_rng(cseed, _KEY_Z).integers(1, 8 + 1, size=natoms).sum())
+        ns = int(min(ns_range[1], max(ns_range[0], (ne + 1) // 2 + 30)))
+        clusters.append(dict(n=n, h=0.45, natoms=natoms, zmax=8, lmax=1, ns=ns, ne=ne,
                              m=int(rng.integers(20, 31)),
-                             fp32=bool(rng.random() < fp32_share), seed=100000 + 1000 * seed + i))
+                             fp32=bool(rng.random() < fp32_share), seed=cseed))
     # interleave the clusters' step requests in arrival order
     pending = [[c, 0] for c in clusters]
     while pending:

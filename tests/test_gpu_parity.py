@@ -264,3 +264,37 @@ def test_lanczos_medium_grid():
     _, _, rt = oracle.lanczos(cl, 40, v0)
     print("medium lanczos max |dtheta|", np.abs(theta - rt).max())
     assert np.abs(theta - rt).max() <= TOL_RITZ
+
+
+@pytest.fixture(scope="module")
+def wide():
+    # the widest orbital block of the serving workload (253 columns) on a 36^3 grid
+    cl = inputs.make_cluster(36, 0.45, 3, 8, 1, seed=31)
+    ns, m, seed = 253, 16, 31
+    X = inputs.orbitals(cl.nd, ns, seed)
+    return cl, ns, m, seed, X, _bounds(cl, seed)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_wide_block_pass(wide, dtype):
+    """Filter, FP64 Rayleigh-Ritz (library eigensolver path) and rotation of a
+    253-column block against the oracle's pass."""
+    cl, ns, m, seed, X, (a0, a, b) = wide
+    binding = _b()
+    op = binding.Operator(cl)
+    if dtype == "f32":
+        clr, Xr, tdt, tol = inputs.round_cluster_f32(cl), inputs.round_to_f32(X), torch.float32, TOL32
+    else:
+        clr, Xr, tdt, tol = cl, X, torch.float64, TOL64
+    Yd = op.cheb_filter(dev(Xr, tdt), m, a0, a, b)
+    ref = oracle.cheb_filter(clr, Xr, m, a0, a, b)
+    err = rel_err(host(Yd), ref)
+    print(f"wide {dtype} filter err {err:.3e}")
+    assert err <= tol
+    theta, Qt = op.rayleigh_ritz(Yd)
+    rt, _, _, _ = oracle.rayleigh_ritz(clr, ref)
+    print(f"wide {dtype} max |dtheta| {np.abs(theta - rt).max():.3e}")
+    assert np.abs(theta - rt).max() <= TOL_RITZ
+    R = host(binding.rotate(Yd, Qt))
+    gram = R @ R.T
+    assert np.abs(gram - np.eye(ns)).max() < (1e-9 if dtype == "f64" else 1e-3)

@@ -64,3 +64,8 @@ def test_batch_and_serving_recipes():
         k = r["cluster"]["seed"]
         assert r["step"] == seen.get(k, -1) + 1
         seen[k] = r["step"]
+    # N_s = N_e/2 + 30 with N_e the sum of the Z that make_cluster draws
+    c = s[0]["cluster"]
+    cl = inputs.make_cluster(c["n"], c["h"], c["natoms"], c["zmax"], c["lmax"], c["seed"])
+    assert c["ne"] == sum(a.Z for a in cl.atoms)
+    assert c["ns"] == min(256, max(8, (c["ne"] + 1) // 2 + 30))
