@@ -5,7 +5,7 @@ Workload: the medium synthetic cluster (96^3 grid, h = 0.4 bohr, 16 atoms with
 stencil order 12).  One step is one filtered-subspace pass over the resident
 orbital block: 40-step FP64 Lanczos bounds on the device, the Chebyshev filter
 in the selected dtype, FP64 Rayleigh-Ritz on the device and the subspace
-rotation.  ``value`` is filtered orbital*gridpoint updates per second of the
+rotation; each pass starts from the orbitals the previous one rotated.  ``value`` is filtered orbital*gridpoint updates per second of the
 whole step (N_d * N_s * m / step time).
 
 Prints ONE JSON line (rank 0).  Defaults: 1 GPU, 10 timed steps, 3 warmup.
@@ -43,7 +43,7 @@ def parse():
     p.add_argument("--batch-only", action="store_true", help="print only the batched measurement")
     p.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     p.add_argument("--serve-only", action="store_true", help="print only the serving measurement")
-    p.add_argument("--serve-rates", default="100",
+    p.add_argument("--serve-rates", default="50",
                    help="comma-separated Poisson arrival rates in requests/s (full sweep: 50,100,200,500,1000,2000)")
     p.add_argument("--serve-requests", type=int, default=500, help="requests per rate point (5 per cluster)")
     p.add_argument("--serve-workers", type=int, default=4)
@@ -124,6 +124,8 @@ class Pass:
             b.profile.enable(False)
         self.ritz, Qt = self.op.rayleigh_ritz(self.Y)
         b.rotate(self.Y, Qt, out=self.R)
+        # the next pass continues from the rotated orbitals, as the SCF passes do
+        self.X, self.R = self.R, self.X
 
     def filter_only(self):
         a0, a, bb = self.bounds
@@ -204,105 +206,119 @@ SERVE_BUDGET = 250e9
 
 class ServeSetup:
     """Clusters of the serving stream (grid edge log-uniform in [24,128], h =
-    0.45, 1-64 atoms, 8-256 orbitals, degree 20-30, FP32:FP64 = 80:20), built
-    once.  Synthetic orbitals and Lanczos starts are prefixes of one seeded
-    N(0,1) device buffer per dtype, which the server copies at admission."""
+    0.45, 1-64 atoms, N_s = N_e/2 + 30, degree 20-30, FP32:FP64 = 80:20),
+    built once.  Synthetic orbitals and Lanczos starts are prefixes of one
+    seeded N(0,1) device buffer per dtype, which the server copies at
+    admission."""
 
     def __init__(self, nclusters):
         import torch
         from paper_1603_04334_amd import binding, inputs
-        self.recipe0 = inputs.serving_recipe(seed=5, nclusters=nclusters, rate=1.0, steps_per_cluster=SERVE_STEPS)
-        specs = {}
-        for r in self.recipe0:
-            specs[r["cluster"]["seed"]] = r["cluster"]
-        self.specs = specs
+        sessions = inputs.serving_recipe(seed=5, nclusters=nclusters, rate=1.0, steps_per_cluster=SERVE_STEPS)
+        self.specs = {r["cluster"]["seed"]: r["cluster"] for r in sessions}
+        specs = self.specs
         maxnd = max(c["n"] ** 3 for c in specs.values())
         maxns = max(c["ns"] for c in specs.values())
         gen = torch.Generator(device="cuda")
         gen.manual_seed(5)
         self.X64 = torch.randn(maxnd * maxns, generator=gen, device="cuda", dtype=torch.float64)
-        self.X32 = self.X64[: maxnd * maxns].float() if any(c["fp32"] for c in specs.values()) else None
+        self.X32 = self.X64.float() if any(c["fp32"] for c in specs.values()) else None
         self.v0 = torch.randn(maxnd, generator=gen, device="cuda", dtype=torch.float64)
         torch.cuda.synchronize()
         self.descs = {}
-        self.work = {}
         for sd, c in specs.items():
             cl = inputs.make_cluster(c["n"], c["h"], c["natoms"], c["zmax"], c["lmax"], sd)
             src = self.X32 if c["fp32"] else self.X64
             X0 = src[: cl.nd * c["ns"]].view(c["ns"], cl.nd)
             self.descs[sd] = binding.cluster_desc(cl, X0, self.v0[: cl.nd], c["m"])
-            self.work[sd] = cl.nd * c["ns"] * c["m"]
 
 
 def serve_point(setup, rate, nclusters, workers):
-    """Open-loop run: requests are submitted at their Poisson arrival times;
-    latency = completion - scheduled arrival (so a slow client cannot hide
-    queueing)."""
+    """Open loop over sessions: a cluster's session arrives at its Poisson time
+    and submits its first pass; each later pass is submitted as soon as the
+    previous one is done (an SCF client waits for its orbitals).  Request
+    latency = completion - submission of the pass; session latency =
+    completion of the last pass - arrival."""
     from paper_1603_04334_amd import binding, inputs
-    reqs = inputs.serving_recipe(seed=5, nclusters=nclusters, rate=rate, steps_per_cluster=SERVE_STEPS)
+    sessions = inputs.serving_recipe(seed=5, nclusters=nclusters, rate=rate, steps_per_cluster=SERVE_STEPS)
     srv = binding.Server(workers=workers, budget=int(SERVE_BUDGET), lanczos_steps=KSTEPS_LANCZOS)
-    tickets = []
-    refused = []
+    done = []          # (session index, pass, result)
+    open_t = {}        # ticket -> (session index, pass)
+    failed_sessions = {}
     lag = 0.0
+    nxt = 0
     try:
         t0 = binding.clock() + 0.01
-        for r in reqs:
-            c = r["cluster"]
-            t_s = t0 + r["t_arrive"]
-            while True:
-                dt = t_s - binding.clock()
-                if dt <= 0:
-                    break
-                time.sleep(dt if dt > 2e-3 else 0)
-            first = r["step"] == 0
-            try:
-                tk = srv.submit(c["seed"], setup.descs[c["seed"]] if first else None,
-                                release=r["step"] == SERVE_STEPS - 1)
-            except binding.SparcError as e:  # the cluster already failed
-                refused.append(e.status)
-                continue
-            lag = max(lag, binding.clock() - t_s)
-            tickets.append((tk, t_s, c["seed"], c["fp32"]))
-        res = {}
         deadline = time.time() + 900
-        while len(res) < len(tickets):
-            for tk, *_ in tickets:
-                if tk not in res:
-                    r = srv.poll(tk)
-                    if r is not None:
-                        res[tk] = r
+        while nxt < len(sessions) or open_t:
+            now = binding.clock()
+            while nxt < len(sessions) and t0 + sessions[nxt]["t_arrive"] <= now:
+                c = sessions[nxt]["cluster"]
+                tk = srv.submit(c["seed"], setup.descs[c["seed"]], release=SERVE_STEPS == 1)
+                lag = max(lag, binding.clock() - (t0 + sessions[nxt]["t_arrive"]))
+                open_t[tk] = (nxt, 0)
+                nxt += 1
+            for tk in list(open_t):
+                r = srv.poll(tk)
+                if r is None:
+                    continue
+                i, k = open_t.pop(tk)
+                done.append((i, k, r))
+                if r["status"] != 0:
+                    failed_sessions[i] = r["status"]
+                elif k + 1 < SERVE_STEPS:
+                    c = sessions[i]["cluster"]
+                    open_t[srv.submit(c["seed"], release=k + 2 == SERVE_STEPS)] = (i, k + 1)
             if time.time() > deadline:
                 raise RuntimeError("serving run did not finish")
-            time.sleep(0.002)
+            wait = (t0 + sessions[nxt]["t_arrive"] - binding.clock()) if nxt < len(sessions) else 1e-3
+            time.sleep(min(max(wait, 0.0), 5e-4))
     finally:
         srv.close()
+    ok = [(i, k, r) for i, k, r in done if r["status"] == 0]
     failed = {}
-    for st in [r["status"] for r in res.values() if r["status"] != 0] + refused:
-        failed[binding.status_name(st)] = failed.get(binding.status_name(st), 0) + 1
-    ok = [(tk, t_s, f) for tk, t_s, _, f in tickets if res[tk]["status"] == 0]
-    lat = np.array([res[tk]["t_end"] - t_s for tk, t_s, _ in ok])
-    lat32 = np.array([res[tk]["t_end"] - t_s for tk, t_s, f in ok if f])
-    lat64 = np.array([res[tk]["t_end"] - t_s for tk, t_s, f in ok if not f])
-    span = max(r["t_end"] for r in res.values()) - t0
-    upd = sum(r["updates"] for r in res.values() if r["status"] == 0)
+    for i, k, r in done:
+        if r["status"] != 0:
+            failed[binding.status_name(r["status"])] = failed.get(binding.status_name(r["status"]), 0) + 1
+    failures = []
+    for i, k, r in done:
+        if r["status"] != 0:
+            c = sessions[i]["cluster"]
+            failures.append({"n": c["n"], "ns": c["ns"], "m": c["m"], "natoms": c["natoms"], "fp32": c["fp32"],
+                             "seed": c["seed"], "pass": k, "status": binding.status_name(r["status"])})
+    lat = np.array([r["t_end"] - r["t_submit"] for _, _, r in ok])
+    is32 = np.array([sessions[i]["cluster"]["fp32"] for i, _, _ in ok])
+    last = {}
+    for i, k, r in ok:
+        if k == SERVE_STEPS - 1:
+            last[i] = r["t_end"] - (t0 + sessions[i]["t_arrive"])
+    sess = np.array(list(last.values()))
+    span = max(r["t_end"] for _, _, r in done) - t0
+    upd = sum(r["updates"] for _, _, r in ok)
     q = lambda a, p: float(np.percentile(a, p) * 1e3) if len(a) else None
-    return {"rate": rate, "requests": len(reqs), "completed": len(ok), "failed": failed, "clusters": nclusters,
-            "p50_ms": q(lat, 50), "p99_ms": q(lat, 99), "mean_ms": float(lat.mean() * 1e3),
-            "p50_ms_f32": q(lat32, 50), "p99_ms_f32": q(lat32, 99), "p50_ms_f64": q(lat64, 50),
-            "p99_ms_f64": q(lat64, 99), "throughput_req_s": len(ok) / span, "updates_per_s": upd / span,
-            "span_s": span, "max_submit_lag_ms": lag * 1e3}
+    return {"rate": rate, "sessions": len(sessions), "requests": len(sessions) * SERVE_STEPS,
+            "completed": len(ok), "failed": failed, "failures": failures[:8],
+            "p50_ms": q(lat, 50), "p99_ms": q(lat, 99), "mean_ms": float(lat.mean() * 1e3) if len(lat) else None,
+            "p50_ms_f32": q(lat[is32], 50), "p99_ms_f32": q(lat[is32], 99),
+            "p50_ms_f64": q(lat[~is32], 50), "p99_ms_f64": q(lat[~is32], 99),
+            "session_p50_ms": q(sess, 50), "session_p99_ms": q(sess, 99),
+            "throughput_req_s": len(ok) / span, "updates_per_s": upd / span, "span_s": span,
+            "max_arrival_lag_ms": lag * 1e3}
 
 
 def serve_measure(rates, nrequests, workers):
     import torch
     nclusters = max(1, nrequests // SERVE_STEPS)
     setup = ServeSetup(nclusters)
-    # warm-up: kernels, rocBLAS/rocSOLVER handles, allocator pools
+    # warm-up: kernels, library handles, allocator pools
     serve_point(setup, 1e6, min(nclusters, 8), workers)
-    points = [serve_point(setup, r, nclusters, workers) for r in rates]
-    out = {"workload": f"{nclusters} clusters x {SERVE_STEPS} filtered-subspace passes (Lanczos bounds on the "
-                       f"first), grid edge log-uniform 24-128, h=0.45, 1-64 atoms, 8-256 orbitals, degree 20-30, "
-                       f"FP32:FP64 = 80:20, Poisson arrivals, open loop",
+    points = []
+    for r in rates:
+        points.append(serve_point(setup, r, nclusters, workers))
+        print(f"serving point done: {json.dumps(points[-1])}", file=sys.stderr, flush=True)
+    out = {"workload": f"{nclusters} cluster sessions x {SERVE_STEPS} filtered-subspace passes (Lanczos bounds on "
+                       f"the first), grid edge log-uniform 24-128, h=0.45, 1-64 atoms, N_s = N_e/2+30, degree 20-30, "
+                       f"FP32:FP64 = 80:20, Poisson session arrivals at rate/{SERVE_STEPS}, passes chained",
            "workers": workers, "budget_bytes": SERVE_BUDGET, "points": points}
     del setup
     torch.cuda.empty_cache()

@@ -184,11 +184,16 @@ size_t sparc_rr_workspace_bytes(const sparc_op *op, int32_t dtype, int32_t ns);
 int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_t ldy, int32_t ns,
                         double *theta, double *evec, void *ws, size_t ws_bytes, void *stream);
 
+/* Workspace bytes of sparc_rotate: a zero-padded copy of Q in dtype. */
+size_t sparc_rotate_workspace_bytes(int32_t dtype, int32_t ns);
+
 /* Subspace rotation Psi = Psi_f Q (Sec. 3.4, Eq. OrbitalTransformation):
  * Y (ldy) is an nd x ns block of the given dtype, Q an FP64 ns x ns
- * column-major device matrix (converted to dtype first when dtype is F32;
- * ws must then hold ns*ns floats, else ws may be NULL), out (ldo) an nd x ns
- * block of dtype that must not overlap Y.  Asynchronous. */
+ * column-major device matrix (rounded to dtype for an FP32 block), ws a device
+ * workspace of sparc_rotate_workspace_bytes(dtype, ns) bytes, out (ldo) an
+ * nd x ns block of dtype.  Sums run in dtype.  Y, out and ws must not
+ * overlap.  Asynchronous.  Errors: SPARC_E_ARG, SPARC_E_SHAPE,
+ * SPARC_E_WORKSPACE, SPARC_E_ALIAS, SPARC_E_HIP. */
 int sparc_rotate(int32_t dtype, const void *Y, int64_t ldy, int64_t nd, int32_t ns, const double *Q,
                  void *out, int64_t ldo, void *ws, size_t ws_bytes, void *stream);
 
@@ -357,15 +362,17 @@ int sparc_profile_reset(void);
 /* Override the launch configuration of the fused step kernel for one dtype:
  * tile extent along z and y (one of 32x16, 32x32, 32x48, 64x8, 64x16) and the number
  * of x-planes per workgroup (chunk_x <= 0: library choice).  tile_z = tile_y
- * = 0 restores the library's tile choice.  Results do not depend on the
- * configuration.  Not thread-safe against calls that use the op.
+ * = 0 restores the library's tile choice.  Applies to blocks of every width.
+ * Results do not depend on the configuration.  Not thread-safe against calls
+ * that use the op.
  * Errors: SPARC_E_ARG (null op, bad dtype, unsupported tile). */
 int sparc_op_set_launch(sparc_op *op, int32_t dtype, int32_t tile_z, int32_t tile_y, int32_t chunk_x);
 
 /* Measure every tile shape and a few x-chunk lengths of the fused step kernel
  * for this op, dtype and column count on scratch blocks (allocated and freed
- * here), apply the fastest to the op as sparc_op_set_launch would, and return
- * it (out params may be NULL; best_us = microseconds per recurrence step).
+ * here), apply the fastest to the op for blocks of ns columns (other widths
+ * keep the library's choice), and return it (out params may be NULL; best_us =
+ * microseconds per recurrence step).
  * Results are cached per (grid, ns, dtype) in the process and, when the
  * environment variable SPARC_TUNE_CACHE names a file, appended to and read
  * from that file.  Synchronous.  Not thread-safe against calls using the op.

@@ -109,6 +109,7 @@ _SIGS = {
     "sparc_op_set_launch": (_i32, [_vp, _i32, _i32, _i32, _i32]),
     "sparc_autotune": (_i32, [_vp, _i32, _i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                               _dp]),
+    "sparc_rotate_workspace_bytes": (ctypes.c_size_t, [_i32, _i32]),
     "sparc_server_create": (_i32, [ctypes.POINTER(sparc_server_cfg), ctypes.POINTER(_vp)]),
     "sparc_filter_submit": (_i32, [_vp, ctypes.POINTER(sparc_filter_job), ctypes.POINTER(ctypes.c_uint64)]),
     "sparc_filter_poll": (_i32, [_vp, ctypes.c_uint64, ctypes.POINTER(sparc_job_result)]),
@@ -313,7 +314,7 @@ def select_bounds(theta, nwant: int = 8, shift: float = 0.1, bfactor: float = 1.
     return a0.value, a.value, b.value
 
 
-def rotate(Y, Qt, out=None, stream=None):
+def rotate(Y, Qt, out=None, ws=None, stream=None):
     """Psi = Psi_f Q; Y and out are (ns, nd) blocks, Qt the (ns, ns) tensor
     returned by ``Operator.rayleigh_ritz`` (column-major Q)."""
     import torch
@@ -322,7 +323,8 @@ def rotate(Y, Qt, out=None, stream=None):
     if out is None:
         out = torch.empty_like(Y)
     dt = _dtype_code(Y)
-    ws = torch.empty(ns * ns * 4 if dt == SPARC_F32 else 1, dtype=torch.uint8, device=Y.device)
+    if ws is None:
+        ws = torch.empty(max(1, int(lib().sparc_rotate_workspace_bytes(dt, ns))), dtype=torch.uint8, device=Y.device)
     check(lib().sparc_rotate(dt, _ptr(Y), ldy, nd, ns, _ptr(Qt), _ptr(out), out.stride(0), _ptr(ws), ws.numel(),
                              _stream(stream)), "sparc_rotate")
     return out

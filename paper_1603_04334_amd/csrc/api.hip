@@ -409,6 +409,7 @@ int sparc_op_set_launch(sparc_op *op, int32_t dtype, int32_t tile_z, int32_t til
         op->tune_shape[dtype] = found;
     }
     op->tune_chunk[dtype] = chunk_x > 0 ? chunk_x : 0;
+    op->tune_ns[dtype] = -1;
     return SPARC_OK;
 }
 

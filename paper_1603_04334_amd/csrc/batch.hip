@@ -477,7 +477,7 @@ int sparc_batch_create(const sparc_batch_job *jobs, int32_t njobs, int32_t mode,
         c.tiles_z = (c.n3 + 31) / 32;
         const long long per = (long long)c.tiles_y * c.tiles_z * ((j.ns + kBatchColGroup - 1) / kBatchColGroup);
         int nch = (int)std::max<long long>(1, std::min<long long>((64 + per - 1) / per, c.n1 / 8));
-        if (op->tune_chunk[j.dtype] > 0) nch = (c.n1 + op->tune_chunk[j.dtype] - 1) / op->tune_chunk[j.dtype];
+        if (tune_applies(op, j.dtype, j.ns) && op->tune_chunk[j.dtype] > 0) nch = (c.n1 + op->tune_chunk[j.dtype] - 1) / op->tune_chunk[j.dtype];
         c.chunk_x = (c.n1 + nch - 1) / nch;
         c.nchunks = (c.n1 + c.chunk_x - 1) / c.chunk_x;
         c.ncb = (j.ns + 15) / 16;

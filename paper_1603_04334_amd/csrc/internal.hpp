@@ -77,6 +77,7 @@ struct sparc_op {
     // launch overrides (set by sparc_op_set_launch; -1 / 0 = library choice)
     int tune_shape[2] = {-1, -1};
     int tune_chunk[2] = {0, 0};
+    int tune_ns[2] = {-1, -1};  // block width the launch choice was tuned for; -1: every width
 };
 
 namespace sparc {
@@ -100,6 +101,9 @@ struct StepCoef {
     double alpha, beta, shift;
     int has_prev;
 };
+
+// launch override of the op for a block of ns columns of the given dtype
+inline bool tune_applies(const sparc_op *op, int dtype, int ns) { return op->tune_ns[dtype] < 0 || op->tune_ns[dtype] == ns; }
 
 struct StepLaunch {
     int shape;     // index into kShapes

@@ -272,6 +272,77 @@ static dim3 stream_grid(long long n)
     return dim3((unsigned)std::min<long long>(b, 4096));
 }
 
+// ---------------------------------------------------------------- rotation
+
+// out(x, c) = sum_j Y(x, j) Q(j, c) for a block of RotTile::cols output
+// columns.  One thread per grid point x: the row of Y is read in chunks of
+// RotTile::k values (each load coalesced along x); Q comes as a zero-padded
+// copy in the block's dtype, column-major with a leading dimension that is a
+// multiple of the chunk, so Q(k0.., c) is contiguous and wave-uniform (scalar
+// loads); each thread keeps the sums of its point in registers and every
+// output column is written coalesced along x.  HBM-bound: Y is read once and
+// out written once per column block.
+template <typename T>
+struct RotTile;
+template <>
+struct RotTile<float> {
+    static constexpr int cols = 64, k = 16;
+};
+template <>
+struct RotTile<double> {
+    static constexpr int cols = 32, k = 16;
+};
+
+inline int rot_ldq(int ns) { return (ns + 15) / 16 * 16; }
+template <typename T>
+inline int rot_ncols(int ns)
+{
+    return (ns + RotTile<T>::cols - 1) / RotTile<T>::cols * RotTile<T>::cols;
+}
+
+// Qp(j, c) = Q(j, c) for j, c < ns, zero elsewhere (ldq x ncp, column-major)
+template <typename T>
+__global__ void pad_rotation(const double *__restrict__ Q, int ns, T *__restrict__ Qp, int ldq, int ncp)
+{
+    const long long total = (long long)ldq * ncp;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int j = (int)(e % ldq), c = (int)(e / ldq);
+        Qp[e] = (j < ns && c < ns) ? (T)Q[(long long)c * ns + j] : T(0);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) rotate_kernel(const T *__restrict__ Y, long long ldy, const T *__restrict__ Qp,
+                                                     int ldq, T *__restrict__ out, long long ldo, long long nd, int ns)
+{
+    constexpr int NC = RotTile<T>::cols, KC = RotTile<T>::k;
+    const long long x = blockIdx.x * 256LL + threadIdx.x;
+    const int c0 = blockIdx.y * NC;
+    const long long xs = x < nd ? x : nd - 1;  // loads stay in bounds; the store is masked
+    T acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = T(0);
+    for (int k0 = 0; k0 < ns; k0 += KC) {
+        T y[KC];
+#pragma unroll
+        for (int j = 0; j < KC; ++j) y[j] = (k0 + j < ns) ? Y[(long long)(k0 + j) * ldy + xs] : T(0);
+        const T *q = Qp + (long long)c0 * ldq + k0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            T t = acc[c];
+#pragma unroll
+            for (int j = 0; j < KC; ++j) t += y[j] * q[(long long)c * ldq + j];
+            acc[c] = t;
+        }
+    }
+    if (x < nd) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (c0 + c < ns) out[(long long)(c0 + c) * ldo + x] = acc[c];
+    }
+}
+
 // ---------------------------------------------------------------- BLAS handles
 
 // rocBLAS handles are not safe for concurrent use, and a handle's device
@@ -554,36 +625,48 @@ int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_
     return SPARC_OK;
 }
 
+size_t sparc_rotate_workspace_bytes(int32_t dtype, int32_t ns)
+{
+    if (ns < 1) return 0;
+    if (dtype == SPARC_F64) return (size_t)rot_ldq(ns) * rot_ncols<double>(ns) * sizeof(double);
+    if (dtype == SPARC_F32) return (size_t)rot_ldq(ns) * rot_ncols<float>(ns) * sizeof(float);
+    return 0;
+}
+
 int sparc_rotate(int32_t dtype, const void *Y, int64_t ldy, int64_t nd, int32_t ns, const double *Q, void *out,
                  int64_t ldo, void *ws, size_t ws_bytes, void *stream)
 {
     if (!Y || !Q || !out) return fail(SPARC_E_ARG, "null argument");
+    if (dtype != SPARC_F64 && dtype != SPARC_F32) return fail(SPARC_E_ARG, "bad dtype");
     if (ns < 1 || nd < 1 || ldy < nd || ldo < nd) return fail(SPARC_E_SHAPE, "bad shape");
-    if (ldy > 0x7fffffffLL || ldo > 0x7fffffffLL || nd > 0x7fffffffLL)
-        return fail(SPARC_E_SHAPE, "dimension exceeds 32 bits");
     const size_t es = elem_size(dtype);
     const size_t by = (size_t)((ns - 1) * ldy + nd) * es, bo = (size_t)((ns - 1) * ldo + nd) * es;
     const char *pa = (const char *)Y, *pb = (const char *)out;
     if (pa < pb + bo && pb < pa + by) return fail(SPARC_E_ALIAS, "Y and out overlap");
+    const size_t need = sparc_rotate_workspace_bytes(dtype, ns);
+    if (!ws || ws_bytes < need) return fail(SPARC_E_WORKSPACE, "workspace too small");
+    const char *pw = (const char *)ws;
+    if ((pw < pa + by && pa < pw + need) || (pw < pb + bo && pb < pw + need))
+        return fail(SPARC_E_ALIAS, "workspace overlaps Y or out");
     hipStream_t s = (hipStream_t)stream;
-    BlasLease lease(s);
-    rocblas_handle hb = lease.h;
-    if (!hb) return fail(SPARC_E_HIP, "rocblas_create_handle failed");
+    const unsigned gx = (unsigned)((nd + 255) / 256);
+    const int ldq = rot_ldq(ns);
     if (dtype == SPARC_F64) {
-        const double one = 1.0, zero = 0.0;
-        if (rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, (int)nd, ns, ns, &one, (const double *)Y,
-                          (int)ldy, Q, ns, &zero, (double *)out, (int)ldo) != rocblas_status_success)
-            return fail(SPARC_E_HIP, "rocblas_dgemm failed");
-        return SPARC_OK;
+        const int ncp = rot_ncols<double>(ns);
+        hipLaunchKernelGGL(pad_rotation<double>, stream_grid((long long)ldq * ncp), dim3(256), 0, s, Q, ns,
+                           (double *)ws, ldq, ncp);
+        hipLaunchKernelGGL(rotate_kernel<double>, dim3(gx, ncp / RotTile<double>::cols), dim3(256), 0, s,
+                           (const double *)Y, (long long)ldy, (const double *)ws, ldq, (double *)out, (long long)ldo,
+                           (long long)nd, ns);
+    } else {
+        const int ncp = rot_ncols<float>(ns);
+        hipLaunchKernelGGL(pad_rotation<float>, stream_grid((long long)ldq * ncp), dim3(256), 0, s, Q, ns,
+                           (float *)ws, ldq, ncp);
+        hipLaunchKernelGGL(rotate_kernel<float>, dim3(gx, ncp / RotTile<float>::cols), dim3(256), 0, s,
+                           (const float *)Y, (long long)ldy, (const float *)ws, ldq, (float *)out, (long long)ldo,
+                           (long long)nd, ns);
     }
-    if (dtype != SPARC_F32) return fail(SPARC_E_ARG, "bad dtype");
-    if (!ws || ws_bytes < (size_t)ns * ns * sizeof(float)) return fail(SPARC_E_WORKSPACE, "workspace too small");
-    hipLaunchKernelGGL(f64_to_f32_dense, stream_grid((long long)ns * ns), dim3(256), 0, s, Q, (float *)ws,
-                       (long long)ns * ns);
-    const float one = 1.0f, zero = 0.0f;
-    if (rocblas_sgemm(hb, rocblas_operation_none, rocblas_operation_none, (int)nd, ns, ns, &one, (const float *)Y,
-                      (int)ldy, (const float *)ws, ns, &zero, (float *)out, (int)ldo) != rocblas_status_success)
-        return fail(SPARC_E_HIP, "rocblas_sgemm failed");
+    SPARC_HIP(hipGetLastError());
     return SPARC_OK;
 }
 

@@ -133,7 +133,7 @@ size_t estimate_footprint(const Cluster &c, int lanczos_k)
     size_t f = nd * 12 + chi * 12 + box * 28 + 4096;                 // operator
     f += 3 * nd * ns * s + 4 * std::max<size_t>(1, nproj) * ns * s;  // X, Y, filter workspace
     f += (c.dtype == SPARC_F32 ? nd * ns * 8 : 0) + nd * ns * 8;      // Rayleigh-Ritz blocks
-    f += 4 * std::max<size_t>(1, nproj) * ns * 8 + 1024 * 2 * ns * ns * 8 + 4 * ns * ns * 8 + 4096;
+    f += 4 * std::max<size_t>(1, nproj) * ns * 8 + 1024 * 2 * ns * ns * 8 + 4 * (ns + 64) * (ns + 64) * 8 + 4096;
     // first request only: Lanczos, and for FP32 the FP64 blocks of the first pass
     size_t first = nd * (lanczos_k + 1) * 8 + 4096 * (lanczos_k + 2) * 8;
     if (c.dtype == SPARC_F32) first = std::max(first, 3 * nd * ns * 8 + 4 * std::max<size_t>(1, nproj) * ns * 8);
@@ -199,7 +199,8 @@ int execute(sparc_server *srv, Cluster &c, const Request &r, hipStream_t s, spar
         if ((st = sparc_op_create(&c.grid, c.veff.data(), (int)at.size(), at.data(), &c.op))) return st;
         c.ws_bytes = sparc_workspace_bytes(c.op, c.dtype, c.ns, 1);
         c.rr_bytes = sparc_rr_workspace_bytes(c.op, c.dtype, c.ns);  // also covers the FP64 pass
-        c.rot_bytes = (size_t)c.ns * c.ns * sizeof(float) + 256;
+        c.rot_bytes = std::max(sparc_rotate_workspace_bytes(SPARC_F64, c.ns),
+                               sparc_rotate_workspace_bytes(SPARC_F32, c.ns));  // the first pass may be FP64
         const size_t blk = (size_t)c.nd * c.ns * es;
         if (hipMallocAsync(&c.X, blk, s) != hipSuccess || hipMallocAsync(&c.Y, blk, s) != hipSuccess ||
             hipMallocAsync(&c.ws, c.ws_bytes, s) != hipSuccess || hipMallocAsync(&c.rr, c.rr_bytes, s) != hipSuccess ||

@@ -50,7 +50,8 @@ StepLaunch choose_step_launch(const sparc_op *op, int dtype, int ns)
     // 32 x 16 patches of 256 threads measured fastest for both dtypes on the
     // 96^3 and larger grids (lowest register footprint, 4-5 waves per SIMD)
     L.shape = 0;
-    if (op->tune_shape[dtype] >= 0) L.shape = op->tune_shape[dtype];
+    const bool tuned = tune_applies(op, dtype, ns);
+    if (tuned && op->tune_shape[dtype] >= 0) L.shape = op->tune_shape[dtype];
     const TileShape &s = kShapes[L.shape];
     const long long tiles = (long long)((op->n[1] + s.ty() - 1) / s.ty()) * ((op->n[2] + s.tz - 1) / s.tz);
     const long long waves = tiles * ns * (s.nt / 64);
@@ -58,7 +59,7 @@ StepLaunch choose_step_launch(const sparc_op *op, int dtype, int ns)
     long long nchunks = (8192 + waves - 1) / waves;
     nchunks = std::max<long long>(1, std::min<long long>(nchunks, op->n[0] / 4));
     L.chunk_x = (int)((op->n[0] + nchunks - 1) / nchunks);
-    if (op->tune_chunk[dtype] > 0) L.chunk_x = std::min(op->n[0], op->tune_chunk[dtype]);
+    if (tuned && op->tune_chunk[dtype] > 0) L.chunk_x = std::min(op->n[0], op->tune_chunk[dtype]);
     return L;
 }
 

@@ -83,6 +83,8 @@ extern "C" int sparc_autotune(sparc_op *op, int32_t dtype, int32_t ns, void *str
         (void)hipEventCreate(&e0);
         (void)hipEventCreate(&e1);
         const int saved_shape = op->tune_shape[dtype], saved_chunk = op->tune_chunk[dtype];
+        const int saved_ns = op->tune_ns[dtype];
+        op->tune_ns[dtype] = ns;
         const int n1 = op->n[0];
         const int chunks[] = {0, n1, (n1 + 1) / 2, (n1 + 3) / 4, (n1 + 7) / 8};
         StepCoef cf{1.0, 0.5, 0.0, 1};
@@ -108,6 +110,7 @@ extern "C" int sparc_autotune(sparc_op *op, int32_t dtype, int32_t ns, void *str
         }
         op->tune_shape[dtype] = saved_shape;
         op->tune_chunk[dtype] = saved_chunk;
+        op->tune_ns[dtype] = saved_ns;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         (void)hipFree(X);
@@ -120,6 +123,7 @@ extern "C" int sparc_autotune(sparc_op *op, int32_t dtype, int32_t ns, void *str
     }
     op->tune_shape[dtype] = best.shape;
     op->tune_chunk[dtype] = best.chunk;
+    op->tune_ns[dtype] = ns;  // the choice holds for this block width only
     if (tile_z) *tile_z = kShapes[best.shape].tz;
     if (tile_y) *tile_y = kShapes[best.shape].ty();
     if (chunk_x) *chunk_x = best.chunk;

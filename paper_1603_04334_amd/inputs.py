@@ -274,16 +274,17 @@ def batch_recipe(seed: int = 4, nclusters: int = 64) -> List[dict]:
 def serving_recipe(seed: int = 5, nclusters: int = 64, rate: float = 200.0,
                    steps_per_cluster: int = 5, edge_range=(24, 128), ns_range=(8, 256),
                    fp32_share: float = 0.8) -> List[dict]:
-    """Serving stream: clusters with grid edge log-uniform in [24,128] (rounded to
-    a multiple of 8), h = 0.45, atoms clamp(round(64 (n/128)^3), 1, 64), degree
-    U{20..30}, FP32 with probability 0.8, each submitted as ``steps_per_cluster``
-    consecutive requests; inter-arrival times are exponential with the given
-    rate (requests per second).  The orbital count follows the paper's rule
-    (Sec. 4) N_s = N_e/2 + 30 with N_e = sum of the cluster's Z (the same Z that
-    ``make_cluster`` draws), clamped to ``ns_range``."""
+    """Serving stream of cluster sessions.  Each session is one cluster with
+    ``steps_per_cluster`` filtered-subspace passes, run one after another;
+    sessions arrive as a Poisson process whose request rate (passes per
+    second) is ``rate``, i.e. sessions at rate / steps_per_cluster.  Clusters:
+    grid edge log-uniform in [24,128] (rounded to a multiple of 8), h = 0.45,
+    atoms clamp(round(64 (n/128)^3), 1, 64), degree U{20..30}, FP32 with
+    probability 0.8.  The orbital count follows the paper's rule (Sec. 4)
+    N_s = N_e/2 + 30 with N_e = sum of the cluster's Z (the same Z that
+    ``make_cluster`` draws), clamped to ``ns_range``.  Returns sessions in
+    arrival order: dicts with the cluster, ``t_arrive`` and ``steps``."""
     rng = _rng(seed, _KEY_MISC, 1)
-    reqs = []
-    t = 0.0
     clusters = []
     for i in range(nclusters):
         e = math.exp(rng.uniform(math.log(edge_range[0]), math.log(edge_range[1])))
@@ -295,14 +296,11 @@ def serving_recipe(seed: int = 5, nclusters: int = 64, rate: float = 200.0,
         clusters.append(dict(n=n, h=0.45, natoms=natoms, zmax=8, lmax=1, ns=ns, ne=ne,
                              m=int(rng.integers(20, 31)),
                              fp32=bool(rng.random() < fp32_share), seed=cseed))
-    # interleave the clusters' step requests in arrival order
-    pending = [[c, 0] for c in clusters]
-    while pending:
-        t += rng.exponential(1.0 / rate)
-        j = int(rng.integers(0, len(pending)))
-        c, s = pending[j]
-        reqs.append(dict(cluster=c, step=s, t_arrive=t))
-        pending[j][1] += 1
-        if pending[j][1] == steps_per_cluster:
-            pending.pop(j)
-    return reqs
+    # arrival gaps come from their own stream, so the clusters do not depend on the rate
+    arr = _rng(seed, _KEY_MISC, 2)
+    t = 0.0
+    sessions = []
+    for c in clusters:
+        t += arr.exponential(steps_per_cluster / rate)
+        sessions.append(dict(cluster=c, t_arrive=t, steps=steps_per_cluster))
+    return sessions

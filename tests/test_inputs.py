@@ -55,15 +55,13 @@ def test_batch_and_serving_recipes():
     assert all(32 <= r["n"] <= 96 and r["n"] % 8 == 0 and 16 <= r["ns"] <= 128 and 16 <= r["m"] <= 28 for r in b)
     assert all(2 <= r["natoms"] <= 24 for r in b)
     s = inputs.serving_recipe(nclusters=10, rate=100.0)
-    assert len(s) == 50
+    assert len(s) == 10 and all(r["steps"] == 5 for r in s)
     t = [r["t_arrive"] for r in s]
     assert all(x < y for x, y in zip(t, t[1:]))
-    # each cluster's steps arrive in order
-    seen = {}
-    for r in s:
-        k = r["cluster"]["seed"]
-        assert r["step"] == seen.get(k, -1) + 1
-        seen[k] = r["step"]
+    # the clusters do not depend on the rate; the arrivals scale with it
+    s2 = inputs.serving_recipe(nclusters=10, rate=200.0)
+    assert [r["cluster"] for r in s2] == [r["cluster"] for r in s]
+    assert np.allclose([r["t_arrive"] for r in s2], [x / 2 for x in t])
     # N_s = N_e/2 + 30 with N_e the sum of the Z that make_cluster draws
     c = s[0]["cluster"]
     cl = inputs.make_cluster(c["n"], c["h"], c["natoms"], c["zmax"], c["lmax"], c["seed"])
