@@ -28,6 +28,8 @@
 //    wait only covers loads issued one full plane earlier.
 //  * yprev is read pointwise and out may alias it: a thread reads yprev(x)
 //    one plane before it writes out(x), and no other thread touches x.
+//  * yprev and out are streamed with non-temporal loads and stores, so the
+//    L2 keeps the values that are reused (halos of Y_k, V_eff) instead.
 #include "step_kernel.hpp"
 
 namespace sparc {

@@ -81,7 +81,7 @@ struct StepKernel {
         for (int r = 0; r < RY; ++r) {
             const long long g = base + (pok[r] ? pofs[r] : 0);
             s.v[r] = a.veff[g];
-            if constexpr (PREV) s.p[r] = yp[g];
+            if constexpr (PREV) s.p[r] = __builtin_nontemporal_load(&yp[g]);  // read once: keep it out of L2
         }
     }
 
@@ -127,7 +127,7 @@ struct StepKernel {
             acc += (vcur[r] - a.shift) * c;
             T res = a.alpha * acc;
             if constexpr (PREV) res -= a.beta * pcur[r];
-            if (pok[r]) po[pbase + pofs[r]] = res;
+            if (pok[r]) __builtin_nontemporal_store(res, &po[pbase + pofs[r]]);  // written once
         }
 #pragma unroll
         for (int r = 0; r < RY; ++r)

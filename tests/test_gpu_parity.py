@@ -298,3 +298,21 @@ def test_wide_block_pass(wide, dtype):
     R = host(binding.rotate(Yd, Qt))
     gram = R @ R.T
     assert np.abs(gram - np.eye(ns)).max() < (1e-9 if dtype == "f64" else 1e-3)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_single_column_matches_block(small, dtype):
+    """A lone column is cut into many more x-chunks than a block of two (the
+    launch keeps the chip busy): the chunking must not change a bit."""
+    c, cl, X, (a0, a, b) = small
+    op = _b().Operator(cl)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    X2 = dev(X[:2], tdt)
+    one = op.h_apply(X2[:1].contiguous())
+    two = op.h_apply(X2)
+    torch.cuda.synchronize()
+    assert torch.equal(one[0], two[0])
+    f1 = op.cheb_filter(X2[1:].contiguous(), 7, a0, a, b)
+    f2 = op.cheb_filter(X2, 7, a0, a, b)
+    torch.cuda.synchronize()
+    assert torch.equal(f1[0], f2[1])
