@@ -145,8 +145,12 @@ int sparc_cheb_filter(const sparc_op *op, int32_t dtype, const void *X, int64_t 
 size_t sparc_lanczos_workspace_bytes(const sparc_op *op, int32_t k);
 
 /* k steps of Lanczos on H in FP64 on the device (Sec. 4: extremal eigenvalues
- * of H by a few Lanczos iterations), with full re-orthogonalisation (classical
- * Gram-Schmidt applied twice per step).  v0: device FP64 start vector of N_d
+ * of H by a few Lanczos iterations), kept semi-orthogonal by partial
+ * re-orthogonalisation: the loss of orthogonality is estimated on the device
+ * from the coefficients (Simon's recurrence) and, whenever an estimate passes
+ * sqrt(eps), that step and the next are orthogonalised against the whole basis
+ * by classical Gram-Schmidt.  T_k then agrees with a fully re-orthogonalised
+ * run to working accuracy.  v0: device FP64 start vector of N_d
  * values (normalised internally, not modified).  Outputs on the host: alpha[k]
  * and beta[k-1] (the tridiagonal T_k, may be NULL) and theta[k], the
  * eigenvalues of T_k in ascending order.  Synchronous (waits for stream).

@@ -38,10 +38,12 @@ __device__ inline double wave_sum(double v)
 // wave-level partial inner products: partial[gw*(nv+1) + i] = sum over wave
 // gw's points of V_i(x) w(x) for i < nv, and of w(x)^2 for i = nv.  Each wave
 // owns a contiguous segment of the vectors; groups of 8 vectors per pass.
+// (run != nullptr and *run == 0: nothing to do)
 __global__ void __launch_bounds__(256) multidot_kernel(const double *__restrict__ V, long long ldv, int nv,
                                                        const double *__restrict__ w, long long n,
-                                                       double *__restrict__ partial)
+                                                       double *__restrict__ partial, const int *run)
 {
+    if (run && !*run) return;
     const int lane = threadIdx.x & 63;
     const long long gw = blockIdx.x * 4LL + (threadIdx.x >> 6);
     const long long nw = gridDim.x * 4LL;
@@ -74,8 +76,9 @@ __global__ void __launch_bounds__(256) multidot_kernel(const double *__restrict_
 // one block per i, fixed tree order.  alpha_out[0] = out[alpha_index] if set;
 // mode 1 stores the square root.
 __global__ void __launch_bounds__(256) finish_sums(const double *partial, int stride, double *out,
-                                                   double *alpha_out, int alpha_index, int mode)
+                                                   double *alpha_out, int alpha_index, int mode, const int *run)
 {
+    if (run && !*run) return;
     __shared__ double red[4];
     const int i = blockIdx.x;
     double v = 0.0;
@@ -93,8 +96,9 @@ __global__ void __launch_bounds__(256) finish_sums(const double *partial, int st
 // w -= sum_i coeff[i] V_i, and partial[gw] = sum over wave gw's points of the new w^2
 __global__ void __launch_bounds__(256) orth_apply_norm(double *w, const double *__restrict__ V, long long ldv, int nv,
                                                        const double *__restrict__ coeff, long long n,
-                                                       double *__restrict__ partial)
+                                                       double *__restrict__ partial, const int *run)
 {
+    if (run && !*run) return;
     const int lane = threadIdx.x & 63;
     const long long gw = blockIdx.x * 4LL + (threadIdx.x >> 6);
     const long long nw = gridDim.x * 4LL;
@@ -112,6 +116,84 @@ __global__ void __launch_bounds__(256) orth_apply_norm(double *w, const double *
     }
     nrm = wave_sum(nrm);
     if (lane == 0) partial[gw] = nrm;
+}
+
+// three-term Lanczos step: w -= alpha_j v_j + beta_{j-1} v_{j-1} (bprev may be
+// null at j = 0); partial[gw] = sum over wave gw's points of the new w^2
+__global__ void __launch_bounds__(256) lanczos_3term(double *w, const double *__restrict__ vj,
+                                                     const double *__restrict__ vjm, const double *alpha,
+                                                     const double *bprev, long long n, double *__restrict__ partial)
+{
+    const int lane = threadIdx.x & 63;
+    const long long gw = blockIdx.x * 4LL + (threadIdx.x >> 6);
+    const long long nw = gridDim.x * 4LL;
+    const long long seg = ((n + nw - 1) / nw + 63) / 64 * 64;
+    const long long beg = gw * seg;
+    const long long end = (beg + seg < n) ? beg + seg : n;
+    const double a = *alpha, b = bprev ? *bprev : 0.0;
+    const double *vm = bprev ? vjm : vj;
+    double nrm = 0.0;
+    for (long long x = beg + lane; x < end; x += 64) {
+        const double r = w[x] - (a * vj[x] + b * vm[x]);
+        w[x] = r;
+        nrm += r * r;
+    }
+    nrm = wave_sum(nrm);
+    if (lane == 0) partial[gw] = nrm;
+}
+
+// Partial reorthogonalisation (Simon's omega recurrence).  Row j of the
+// estimates holds v_j^T v_i, i < j; after the three-term step of step j
+// (coefficients alpha_j and beta_j), for i < j
+//   beta_j w'_i = beta_i w_{i+1} + (alpha_i - alpha_j) w_i + beta_{i-1} w_{i-1}
+//                 - beta_{j-1} w''_i  (+ eps1 (beta_i + beta_j) for rounding),
+// w = row j, w'' = row j-1, and w'_j = eps1 ||T|| / beta_j.  The new vector
+// is orthogonalised against the whole basis when an estimate passes sqrt(eps)
+// and, after that, once more on the next step; its row then restarts at eps1.
+// state[0]: orthogonalise the vector of this step; state[1]: owe the next one.
+__global__ void __launch_bounds__(64) omega_kernel(const double *alpha, const double *beta, int j, double eps1,
+                                                   const double *Wp, const double *Wc, double *Wn, int *state,
+                                                   double *anorm)
+{
+    const int lane = threadIdx.x;
+    const double aj = alpha[j], bj = beta[j], bjm = j > 0 ? beta[j - 1] : 0.0;
+    const double an = fmax(*anorm, fabs(aj) + bj + bjm);
+    double mx = 0.0;
+    for (int i = lane; i < j; i += 64) {
+        double t = beta[i] * Wc[i + 1] + (alpha[i] - aj) * Wc[i] - bjm * Wp[i];
+        if (i > 0) t += beta[i - 1] * Wc[i - 1];
+        t += copysign(eps1 * (beta[i] + bj), t);
+        mx = fmax(mx, fabs(t / bj));
+    }
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    const double dj = eps1 * an / bj;
+    const bool owed = state[1] != 0;
+    const bool full = owed || fmax(mx, dj) > 1.4901161193847656e-08;  // sqrt(eps)
+    // second pass for the row values (cheap, avoids holding them across the reduction)
+    for (int i = lane; i < j; i += 64) {
+        double t = beta[i] * Wc[i + 1] + (alpha[i] - aj) * Wc[i] - bjm * Wp[i];
+        if (i > 0) t += beta[i - 1] * Wc[i - 1];
+        t += copysign(eps1 * (beta[i] + bj), t);
+        Wn[i] = full ? eps1 : t / bj;
+    }
+    if (lane == 0) {
+        Wn[j] = full ? eps1 : dj;
+        Wn[j + 1] = 1.0;
+        *anorm = an;
+        state[0] = full ? 1 : 0;
+        state[1] = (full && !owed) ? 1 : 0;
+    }
+}
+
+// state = {0, 0}, anorm = 0, rows j = 0 (1 at i = 0) and j = -1 (zero)
+__global__ void omega_init(double *rows, int len, int *state, double *anorm)
+{
+    for (int i = threadIdx.x; i < 3 * len; i += blockDim.x) rows[i] = (i == 0) ? 1.0 : 0.0;
+    if (threadIdx.x == 0) {
+        state[0] = 0;
+        state[1] = 0;
+        *anorm = 0.0;
+    }
 }
 
 // dst = src / *norm
@@ -460,6 +542,8 @@ size_t sparc_lanczos_workspace_bytes(const sparc_op *op, int32_t k)
     b += gather_bytes(op, SPARC_F64, 1);                                  // gathered projections
     b += align_up((size_t)(4 * k + 8) * sizeof(double));                  // alpha, beta, coeff, norm
     b += align_up((size_t)kRedWaves * (k + 2) * sizeof(double));          // partial sums
+    b += align_up((size_t)(3 * (k + 2) + 1) * sizeof(double));            // omega rows, ||T|| estimate
+    b += align_up(2 * sizeof(int));                                         // reorthogonalisation state
     return b;
 }
 
@@ -489,30 +573,54 @@ int sparc_lanczos(const sparc_op *op, int32_t k, const double *v0, double *alpha
     double *d_norm = d_coeff + k + 2;
     p += align_up((size_t)(4 * k + 8) * sizeof(double));
     double *partial = (double *)p;
+    p += align_up((size_t)kRedWaves * (k + 2) * sizeof(double));
+    double *rows = (double *)p;  // three rows of orthogonality estimates, k + 2 entries each
+    double *d_anorm = rows + 3 * (k + 2);
+    p += align_up((size_t)(3 * (k + 2) + 1) * sizeof(double));
+    int *d_state = (int *)p;
     double *w = V + (long long)k * n;
+    const double eps1 = 0.5 * std::sqrt((double)n) * 2.220446049250313e-16;
 
     const dim3 sg = stream_grid(n);
+    const dim3 rg(kRedBlocks), tb(256);
+    const int *always = nullptr;
     int st;
+    hipLaunchKernelGGL(omega_init, dim3(1), tb, 0, s, rows, k + 2, d_state, d_anorm);
     // V_0 = v0 / |v0|
-    hipLaunchKernelGGL(multidot_kernel, dim3(kRedBlocks), dim3(256), 0, s, v0, (long long)n, 0, v0, n, partial);
-    hipLaunchKernelGGL(finish_sums, dim3(1), dim3(256), 0, s, partial, 1, d_norm, nullptr, -1, 1);
-    hipLaunchKernelGGL(scale_by_inverse, sg, dim3(256), 0, s, V, v0, d_norm, n);
+    hipLaunchKernelGGL(multidot_kernel, rg, tb, 0, s, v0, (long long)n, 0, v0, n, partial, always);
+    hipLaunchKernelGGL(finish_sums, dim3(1), tb, 0, s, partial, 1, d_norm, nullptr, -1, 1, always);
+    hipLaunchKernelGGL(scale_by_inverse, sg, tb, 0, s, V, v0, d_norm, n);
     StepLaunch L = choose_step_launch(op, SPARC_F64, 1);
     StepCoef hc{1.0, 0.0, 0.0, 0};
     for (int j = 0; j < k; ++j) {
         double *vj = V + (long long)j * n;
         if ((st = launch_h_step(op, SPARC_F64, vj, n, nullptr, 0, w, n, 1, G, hc, L, s))) return st;
+        // alpha_j = v_j^T w
+        hipLaunchKernelGGL(multidot_kernel, rg, tb, 0, s, vj, (long long)n, 1, w, n, partial, always);
+        hipLaunchKernelGGL(finish_sums, dim3(1), tb, 0, s, partial, 2, d_coeff, d_alpha + j, 0, 0, always);
+        if (j + 1 == k) break;
+        // w -= alpha_j v_j + beta_{j-1} v_{j-1};  beta_j = |w|
+        hipLaunchKernelGGL(lanczos_3term, rg, tb, 0, s, w, (const double *)vj, (const double *)(vj - (j > 0 ? n : 0)),
+                           (const double *)(d_alpha + j), (const double *)(j > 0 ? d_beta + j - 1 : nullptr), n,
+                           partial);
+        hipLaunchKernelGGL(finish_sums, dim3(1), tb, 0, s, partial, 1, d_beta + j, nullptr, -1, 1, always);
+        // estimate the loss of orthogonality; when needed, one classical
+        // Gram-Schmidt pass against v_0 .. v_j and a new beta_j
+        const double *Wc = rows + (size_t)(j % 3) * (k + 2);
+        const double *Wp = rows + (size_t)((j + 2) % 3) * (k + 2);
+        double *Wn = rows + (size_t)((j + 1) % 3) * (k + 2);
+        hipLaunchKernelGGL(omega_kernel, dim3(1), dim3(64), 0, s, (const double *)d_alpha, (const double *)d_beta, j,
+                           eps1, Wp, Wc, Wn, d_state, d_anorm);
         const int nv = j + 1;
-        hipLaunchKernelGGL(multidot_kernel, dim3(kRedBlocks), dim3(256), 0, s, V, (long long)n, nv, w, n, partial);
-        hipLaunchKernelGGL(finish_sums, dim3(nv + 1), dim3(256), 0, s, partial, nv + 1, d_coeff, d_alpha + j, j, 0);
-        if (j + 1 < k) {
-            hipLaunchKernelGGL(orth_apply_norm, dim3(kRedBlocks), dim3(256), 0, s, w, V, (long long)n, nv, d_coeff, n,
-                               partial);
-            hipLaunchKernelGGL(finish_sums, dim3(1), dim3(256), 0, s, partial, 1, d_beta + j, nullptr, -1, 1);
-            hipLaunchKernelGGL(scale_by_inverse, sg, dim3(256), 0, s, vj + n, w, d_beta + j, n);
-        }
+        const int *full = d_state;
+        hipLaunchKernelGGL(multidot_kernel, rg, tb, 0, s, V, (long long)n, nv, w, n, partial, full);
+        hipLaunchKernelGGL(finish_sums, dim3(nv), tb, 0, s, partial, nv + 1, d_coeff, nullptr, -1, 0, full);
+        hipLaunchKernelGGL(orth_apply_norm, rg, tb, 0, s, w, V, (long long)n, nv, d_coeff, n, partial, full);
+        hipLaunchKernelGGL(finish_sums, dim3(1), tb, 0, s, partial, 1, d_beta + j, nullptr, -1, 1, full);
+        hipLaunchKernelGGL(scale_by_inverse, sg, tb, 0, s, vj + n, w, d_beta + j, n);
         SPARC_HIP(hipGetLastError());
     }
+    SPARC_HIP(hipGetLastError());
     std::vector<double> ha(k), hb(std::max(1, k - 1));
     SPARC_HIP(hipMemcpyAsync(ha.data(), d_alpha, k * sizeof(double), hipMemcpyDeviceToHost, s));
     if (k > 1) SPARC_HIP(hipMemcpyAsync(hb.data(), d_beta, (k - 1) * sizeof(double), hipMemcpyDeviceToHost, s));

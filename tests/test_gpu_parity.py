@@ -316,3 +316,19 @@ def test_single_column_matches_block(small, dtype):
     f2 = op.cheb_filter(X2, 7, a0, a, b)
     torch.cuda.synchronize()
     assert torch.equal(f1[0], f2[1])
+
+
+@pytest.mark.parametrize("n,k", [(10, 200), (12, 300)])
+def test_lanczos_long_run_stays_orthogonal(n, k):
+    """Long runs on small grids lose orthogonality in the three-term recurrence;
+    the device's partial re-orthogonalisation must keep T_k equal to the fully
+    re-orthogonalised oracle's (a loss would show up as spurious copies of
+    converged Ritz values)."""
+    cl = inputs.make_cluster(n, 0.5, 1, 4, 1, seed=n, margin=1.5, min_dist=0.0)
+    v0 = inputs.lanczos_start(cl.nd, n)
+    op = _b().Operator(cl)
+    alpha, beta, theta = op.lanczos(k, dev(v0))
+    ra, rb, rt = oracle.lanczos(cl, k, v0)
+    print(f"n={n} k={k} max |dtheta| {np.abs(theta - rt).max():.2e} |dalpha| {np.abs(alpha - ra).max():.2e}")
+    assert np.abs(theta - rt).max() <= TOL_RITZ
+    assert np.abs(alpha - ra).max() <= 1e-8 and np.abs(beta - rb).max() <= 1e-8
