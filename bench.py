@@ -285,7 +285,8 @@ def serve_point(setup, rate, nclusters, workers):
         if r["status"] != 0:
             c = sessions[i]["cluster"]
             failures.append({"n": c["n"], "ns": c["ns"], "m": c["m"], "natoms": c["natoms"], "fp32": c["fp32"],
-                             "seed": c["seed"], "pass": k, "status": binding.status_name(r["status"])})
+                             "seed": c["seed"], "pass": k, "status": binding.status_name(r["status"]),
+                             "error": r.get("error", "")})
     lat = np.array([r["t_end"] - r["t_submit"] for _, _, r in ok])
     is32 = np.array([sessions[i]["cluster"]["fp32"] for i, _, _ in ok])
     last = {}

@@ -313,6 +313,7 @@ typedef struct {
     double t_submit, t_start, t_end;
     double lambda_min;
     int64_t updates;
+    char error[128];  /* message of the failing call (empty on success) */
 } sparc_job_result;
 
 typedef struct sparc_server sparc_server;

@@ -75,7 +75,7 @@ class sparc_filter_job(ctypes.Structure):
 class sparc_job_result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("step", ctypes.c_int32), ("t_submit", ctypes.c_double),
                 ("t_start", ctypes.c_double), ("t_end", ctypes.c_double), ("lambda_min", ctypes.c_double),
-                ("updates", ctypes.c_int64)]
+                ("updates", ctypes.c_int64), ("error", ctypes.c_char * 128)]
 
 
 _lib = None
@@ -463,7 +463,7 @@ class Server:
             return None
         check(st, "sparc_filter_poll")
         return {"status": r.status, "step": r.step, "t_submit": r.t_submit, "t_start": r.t_start, "t_end": r.t_end,
-                "lambda_min": r.lambda_min, "updates": r.updates}
+                "lambda_min": r.lambda_min, "updates": r.updates, "error": r.error.decode(errors="replace")}
 
     def stats(self):
         d, p, r, u = _i64(), _i64(), _i64(), ctypes.c_uint64()

@@ -4,8 +4,9 @@
 // SubspaceGeneralizedEigenproblem) for n <= kEigMax in a single workgroup
 // with every matrix in LDS:
 //   1. Cholesky factorisation M_s = L L^T (column by column);
-//   2. reduction to standard form C = L^{-1} H_s L^{-T} by two triangular
-//      solves (one thread per column);
+//   2. X = L^{-1} by forward substitution, row by row with every column and
+//      16 partial sums per entry in parallel, then C = X H_s X^T by two
+//      small products (each thread a 2 x 2 block);
 //   3. cyclic Jacobi on C with the round-robin (circle) ordering, so the n/2
 //      rotations of a round touch disjoint rows/columns.  A round is applied
 //      as one two-sided update: one wave computes the round's rotations, and
@@ -16,7 +17,7 @@
 //      Sweeps stop when the off-diagonal mass is below 1e-30 of the total
 //      (relative 1e-15 in norm) or after max_sweeps;
 //   4. eigenvalues sorted ascending (stable), eigenvectors back-transformed
-//      q = L^{-T} z so that Q^T M_s Q = I.
+//      q = X^T z so that Q^T M_s Q = I.
 // Rotation for the pair (p, q): tau = (c_qq - c_pp) / (2 c_pq),
 // t = sign(tau) / (|tau| + sqrt(1 + tau^2)), c = 1/sqrt(1 + t^2), s = t c;
 // rows and columns p, q are replaced by (c x_p - s x_q, s x_p + c x_q), which
@@ -37,6 +38,33 @@ __device__ inline double block_sum_eig(double v, double *red)
     double t = 0.0;
     for (int w = 0; w < kEigThreads / 64; ++w) t += red[w];
     return t;
+}
+
+// D = op(A) op(B) (op: optional transpose) for n x n matrices in LDS, each
+// thread a 2 x 2 block of D; entries of D beyond n are not written.  The
+// caller synchronises.
+__device__ inline void lds_gemm(const double (*A)[kEigMax + 1], const double (*B)[kEigMax + 1],
+                                double (*D)[kEigMax + 1], int n, bool transa, bool transb)
+{
+    const int half = (n + 1) / 2;
+    for (int e = threadIdx.x; e < half * half; e += blockDim.x) {
+        const int r0 = 2 * (e / half), c0 = 2 * (e % half);
+        const int r1 = min(r0 + 1, n - 1), c1 = min(c0 + 1, n - 1);
+        double d00 = 0.0, d01 = 0.0, d10 = 0.0, d11 = 0.0;
+        for (int k = 0; k < n; ++k) {
+            const double a0 = transa ? A[k][r0] : A[r0][k], a1 = transa ? A[k][r1] : A[r1][k];
+            const double b0 = transb ? B[c0][k] : B[k][c0];
+            const double b1 = transb ? B[c1][k] : B[k][c1];
+            d00 += a0 * b0;
+            d01 += a0 * b1;
+            d10 += a1 * b0;
+            d11 += a1 * b1;
+        }
+        D[r0][c0] = d00;
+        if (c0 + 1 < n) D[r0][c0 + 1] = d01;
+        if (r0 + 1 < n) D[r0 + 1][c0] = d10;
+        if (r0 + 1 < n && c0 + 1 < n) D[r0 + 1][c0 + 1] = d11;
+    }
 }
 
 // Jacobi rotation (c, s) annihilating C[p][q], for a pair of the round;
@@ -122,28 +150,34 @@ __global__ void __launch_bounds__(kEigThreads) small_sygv_kernel(const double *_
         return;
     }
 
-    // 2. W = L^{-1} H (columns), then C = L^{-1} W^T, held in Z then copied
-    if (tid < n) {
-        const int c = tid;
-        for (int i = 0; i < n; ++i) {
-            double s = C[i][c];
-            for (int k = 0; k < i; ++k) s -= L[i][k] * C[k][c];
-            C[i][c] = s / L[i][i];
-        }
+    // 2. X = L^{-1} (in Z): row i needs rows k < i; 16 lanes share each entry
+    for (int i = 0; i < n; ++i) {
+        const int c = tid >> 4, part = tid & 15;
+        double acc = 0.0;
+        if (c < i)
+            for (int k = c + part; k < i; k += 16) acc += L[i][k] * Z[k][c];
+        for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+        if (part == 0 && c < n) Z[i][c] = c < i ? -acc / L[i][i] : (c == i ? 1.0 / L[i][i] : 0.0);
+        __syncthreads();
     }
+    // W = X H_s (CB[1]), C = W X^T (CB[0]), symmetrised
+    double (*W)[kEigMax + 1] = CB[1];
+    lds_gemm(Z, C, W, n, false, false);
     __syncthreads();
-    if (tid < n) {
-        const int c = tid;
-        for (int i = 0; i < n; ++i) {
-            double s = C[c][i];
-            for (int k = 0; k < i; ++k) s -= L[i][k] * Z[k][c];
-            Z[i][c] = s / L[i][i];
-        }
-    }
+    lds_gemm(W, Z, C, n, false, true);
     __syncthreads();
     for (int e = tid; e < n * n; e += nt) {
         const int i = e % n, j = e / n;
-        C[i][j] = 0.5 * (Z[i][j] + Z[j][i]);
+        if (i < j) {
+            const double v = 0.5 * (C[i][j] + C[j][i]);
+            C[i][j] = v;
+            C[j][i] = v;
+        }
+    }
+    // keep X for the back-transform in L (the factor is no longer needed)
+    for (int e = tid; e < n * n; e += nt) {
+        const int i = e % n, j = e / n;
+        L[i][j] = Z[i][j];
     }
     __syncthreads();
     for (int e = tid; e < n * np; e += nt) {
@@ -207,7 +241,7 @@ __global__ void __launch_bounds__(kEigThreads) small_sygv_kernel(const double *_
     }
     C = CB[cur];
 
-    // 4. sort (stable ascending) and back-transform q = L^{-T} z (into the other buffer)
+    // 4. sort (stable ascending) and back-transform q = X^T z (into the other buffer)
     double(*Q)[kEigMax + 1] = CB[cur ^ 1];
     if (tid < n) lam[tid] = C[tid][tid];
     __syncthreads();
@@ -219,14 +253,8 @@ __global__ void __launch_bounds__(kEigThreads) small_sygv_kernel(const double *_
         theta[rk] = li;
     }
     __syncthreads();
-    if (tid < n) {
-        const int c = tid;
-        for (int k = n - 1; k >= 0; --k) {
-            double s = Z[k][c];
-            for (int m = k + 1; m < n; ++m) s -= L[m][k] * Q[m][c];
-            Q[k][c] = s / L[k][k];
-        }
-    }
+    // Q = X^T Z
+    lds_gemm(L, Z, Q, n, true, false);
     __syncthreads();
     for (int e = tid; e < n * n; e += nt) {
         const int k = e % n, c = e / n;

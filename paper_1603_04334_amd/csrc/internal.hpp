@@ -15,7 +15,7 @@ namespace sparc {
 constexpr int kMaxRadius = 6;    // largest stencil half-width n_o supported
 constexpr int kMaxProj = 16;     // largest projector count per atom
 constexpr int kBlock = 256;      // threads per workgroup of the stencil kernels
-constexpr int kGatherSplit = 4;  // workgroups sharing one atom's cube points in the gather
+constexpr int kGatherSplit = 8;  // workgroups sharing one atom's cube points in the gather
 constexpr int kScatterSlots = 32;  // most atoms one scatter block may touch
 
 // Per-atom record used by the device kernels.

@@ -463,12 +463,18 @@ struct BlasLease {
                 }
         }
         if (!found) {
-            if (rocblas_create_handle(&e.h) != rocblas_status_success) return;
-            if (hipEventCreateWithFlags(&e.done, hipEventDisableTiming) != hipSuccess) {
-                rocblas_destroy_handle(e.h);
+            // handles are created one at a time (creation is not documented as thread-safe)
+            std::lock_guard<std::mutex> lk(g_blas_mu);
+            if (rocblas_create_handle(&e.h) != rocblas_status_success) {
+                e.h = nullptr;
                 return;
             }
-            // no atomics: GEMM results must not depend on scheduling
+            if (hipEventCreateWithFlags(&e.done, hipEventDisableTiming) != hipSuccess) {
+                rocblas_destroy_handle(e.h);
+                e.h = nullptr;
+                return;
+            }
+            // no atomics: results must not depend on scheduling
             rocblas_set_atomics_mode(e.h, rocblas_atomics_not_allowed);
         }
         rocblas_set_stream(e.h, s);

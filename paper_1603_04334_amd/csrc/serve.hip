@@ -276,7 +276,10 @@ void worker_main(sparc_server *srv)
         res.t_submit = r.t_submit;
         res.t_start = now_s();
         res.status = execute(srv, c, r, s, res);
-        if (res.status != SPARC_OK) (void)hipStreamSynchronize(s);
+        if (res.status != SPARC_OK) {
+            (void)hipStreamSynchronize(s);
+            std::strncpy(res.error, sparc_last_error(), sizeof(res.error) - 1);
+        }
         res.t_end = now_s();
 
         lk.lock();
@@ -300,6 +303,7 @@ void worker_main(sparc_server *srv)
             if (ci != srv->clusters.end() && ci->second->released) {
                 sparc_job_result fr{};
                 fr.status = SPARC_E_JOB;
+                std::strncpy(fr.error, "an earlier request of this cluster failed", sizeof(fr.error) - 1);
                 fr.step = p->step;
                 fr.t_submit = p->t_submit;
                 fr.t_start = fr.t_end = now_s();

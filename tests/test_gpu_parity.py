@@ -332,3 +332,29 @@ def test_lanczos_long_run_stays_orthogonal(n, k):
     print(f"n={n} k={k} max |dtheta| {np.abs(theta - rt).max():.2e} |dalpha| {np.abs(alpha - ra).max():.2e}")
     assert np.abs(theta - rt).max() <= TOL_RITZ
     assert np.abs(alpha - ra).max() <= 1e-8 and np.abs(beta - rb).max() <= 1e-8
+
+
+def test_large_sampled_columns():
+    """Largest single-GPU workload (160^3 grid, 128 atoms with 9 projectors
+    each, 600 orbitals, degree 30) in FP32: three sampled columns against the
+    FP64 oracle fed the same FP32-rounded inputs, and column independence at
+    full size."""
+    c = inputs.LARGE
+    cl = inputs.case_cluster(c.name)
+    cols = [0, 299, 599]
+    a0, a, b = -5.0, 3.0, oracle.upper_bound(cl)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(c.seed)
+    X = torch.randn(c.ns, cl.nd, generator=gen, device="cuda", dtype=torch.float32)
+    Xs = inputs.round_to_f32(inputs.orbitals(cl.nd, c.ns, c.seed, cols=cols))
+    X[cols] = dev(Xs, torch.float32)
+    op = _b().Operator(cl)
+    Y = op.cheb_filter(X, c.m, a0, a, b)
+    got = host(Y[cols])
+    del Y
+    ref = oracle.cheb_filter(inputs.round_cluster_f32(cl), Xs, c.m, a0, a, b)
+    e32 = rel_err(got, ref)
+    print("large sampled error f32 %.3e" % e32)
+    assert e32 <= TOL32
+    one = host(op.cheb_filter(X[cols[1]:cols[1] + 1].contiguous(), c.m, a0, a, b))
+    assert np.array_equal(one[0], got[1])

@@ -180,7 +180,8 @@ def test_serve_wide_blocks_concurrent():
     b = _b()
     alone = {i: _serve(b, [i], 3, workers=1)[0][i] for i in WIDE}
     mixed, res, _ = _serve(b, WIDE, 3, workers=4)
-    assert all(r["status"] == 0 for r in res.values())
+    bad = {k: (r["status"], r["error"]) for k, r in res.items() if r["status"] != 0}
+    assert not bad, f"failed requests (cluster, pass) -> (status, error): {bad}"
     for i in WIDE:
         for s in range(3):
             assert np.array_equal(alone[i][s], mixed[i][s]), f"cluster {i} step {s}"
@@ -274,7 +275,7 @@ def test_serve_errors_and_failure_isolation():
         tb1 = srv.submit(9)
         tg1 = srv.submit(2, release=True)
         res = _wait(srv, [tg0, tb0, tb1, tg1])
-        assert res[tb0]["status"] == SPARC_E_ARG
+        assert res[tb0]["status"] == SPARC_E_ARG and "N_d" in res[tb0]["error"]
         assert res[tb1]["status"] == SPARC_E_JOB
         with pytest.raises(SparcError) as e:
             srv.submit(9)
