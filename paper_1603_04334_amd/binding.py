@@ -134,6 +134,12 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                                "(the HIP library is required; there is no fallback)")
+        # Load torch's HIP runtime first when torch is present: the library then
+        # binds to the same runtime instance as the tensors it is handed.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)

@@ -17,6 +17,7 @@ constexpr int kMaxProj = 16;     // largest projector count per atom
 constexpr int kBlock = 256;      // threads per workgroup of the stencil kernels
 constexpr int kGatherSplit = 8;  // workgroups sharing one atom's cube points in the gather
 constexpr int kScatterSlots = 32;  // most atoms one scatter block may touch
+constexpr double kStreamBytes = 256.0 * 1024 * 1024;  // last-level cache of the chip
 
 // Per-atom record used by the device kernels.
 struct AtomDev {

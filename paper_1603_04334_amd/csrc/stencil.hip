@@ -28,8 +28,10 @@
 //    wait only covers loads issued one full plane earlier.
 //  * yprev is read pointwise and out may alias it: a thread reads yprev(x)
 //    one plane before it writes out(x), and no other thread touches x.
-//  * yprev and out are streamed with non-temporal loads and stores, so the
-//    L2 keeps the values that are reused (halos of Y_k, V_eff) instead.
+//  * When the three blocks of a step exceed the last-level (Infinity) cache,
+//    yprev and out are streamed with non-temporal loads and stores, so the
+//    L2 keeps the values that are reused (halos of Y_k, V_eff) instead;
+//    smaller blocks stay cached from one step to the next.
 #include "step_kernel.hpp"
 
 namespace sparc {
@@ -37,10 +39,10 @@ namespace sparc {
 const TileShape kShapes[kNumShapes] = {{32, 2, 256}, {32, 2, 512}, {32, 2, 768}, {64, 2, 256},
                                        {64, 2, 512}, {32, 4, 256}};
 
-template <typename T, int TZ, int RY, int NT, bool PREV>
+template <typename T, int TZ, int RY, int NT, bool PREV, bool STREAM>
 __global__ void __launch_bounds__(NT) step_kernel(const StepArgs<T> a)
 {
-    using K = StepKernel<T, TZ, RY, NT, PREV>;
+    using K = StepKernel<T, TZ, RY, NT, PREV, STREAM>;
     __shared__ T lds[2][K::SY * K::SZ];
     K k(a);
     k.run(blockIdx.x, lds);
@@ -66,12 +68,17 @@ StepLaunch choose_step_launch(const sparc_op *op, int dtype, int ns)
 }
 
 template <typename T, int TZ, int RY, int NT>
-static int launch_typed(const StepArgs<T> &a, bool prev, hipStream_t stream)
+static int launch_typed(const StepArgs<T> &a, bool prev, bool strm, hipStream_t stream)
 {
-    if (prev)
-        hipLaunchKernelGGL((step_kernel<T, TZ, RY, NT, true>), dim3(a.nblocks), dim3(NT), 0, stream, a);
+    const dim3 g(a.nblocks), b(NT);
+    if (prev && strm)
+        hipLaunchKernelGGL((step_kernel<T, TZ, RY, NT, true, true>), g, b, 0, stream, a);
+    else if (prev)
+        hipLaunchKernelGGL((step_kernel<T, TZ, RY, NT, true, false>), g, b, 0, stream, a);
+    else if (strm)
+        hipLaunchKernelGGL((step_kernel<T, TZ, RY, NT, false, true>), g, b, 0, stream, a);
     else
-        hipLaunchKernelGGL((step_kernel<T, TZ, RY, NT, false>), dim3(a.nblocks), dim3(NT), 0, stream, a);
+        hipLaunchKernelGGL((step_kernel<T, TZ, RY, NT, false, false>), g, b, 0, stream, a);
     SPARC_HIP(hipGetLastError());
     return SPARC_OK;
 }
@@ -107,14 +114,16 @@ static int launch_step_t(const sparc_op *op, const void *yk, int64_t ldk, const 
     a.alpha = (T)c.alpha;
     a.beta = (T)c.beta;
     a.shift = (T)c.shift;
+    // blocks the last-level cache cannot keep between steps are streamed
+    const bool strm = 3.0 * (double)op->nd * ns * sizeof(T) > kStreamBytes;
     ProfScope prof(prev ? 0 : 3, stream);
     switch (L.shape) {
-        case 0: return launch_typed<T, 32, 2, 256>(a, prev, stream);
-        case 1: return launch_typed<T, 32, 2, 512>(a, prev, stream);
-        case 2: return launch_typed<T, 32, 2, 768>(a, prev, stream);
-        case 3: return launch_typed<T, 64, 2, 256>(a, prev, stream);
-        case 4: return launch_typed<T, 64, 2, 512>(a, prev, stream);
-        case 5: return launch_typed<T, 32, 4, 256>(a, prev, stream);
+        case 0: return launch_typed<T, 32, 2, 256>(a, prev, strm, stream);
+        case 1: return launch_typed<T, 32, 2, 512>(a, prev, strm, stream);
+        case 2: return launch_typed<T, 32, 2, 768>(a, prev, strm, stream);
+        case 3: return launch_typed<T, 64, 2, 256>(a, prev, strm, stream);
+        case 4: return launch_typed<T, 64, 2, 512>(a, prev, strm, stream);
+        case 5: return launch_typed<T, 32, 4, 256>(a, prev, strm, stream);
     }
     return fail(SPARC_E_ARG, "unknown tile shape");
 }

@@ -23,7 +23,8 @@ struct StepArgs {
     T alpha, beta, shift;
 };
 
-template <typename T, int TZ, int RY, int NT, bool PREV>
+// STREAM: Y_{k-1} and the output bypass the caches (non-temporal accesses)
+template <typename T, int TZ, int RY, int NT, bool PREV, bool STREAM = false>
 struct StepKernel {
     static constexpr int R = kMaxRadius;
     static constexpr int QL = 2 * R + 1;     // queue length: planes x-R .. x+R
@@ -81,7 +82,12 @@ struct StepKernel {
         for (int r = 0; r < RY; ++r) {
             const long long g = base + (pok[r] ? pofs[r] : 0);
             s.v[r] = a.veff[g];
-            if constexpr (PREV) s.p[r] = __builtin_nontemporal_load(&yp[g]);  // read once: keep it out of L2
+            if constexpr (PREV) {
+                if constexpr (STREAM)
+                    s.p[r] = __builtin_nontemporal_load(&yp[g]);  // read once: keep it out of the caches
+                else
+                    s.p[r] = yp[g];
+            }
         }
     }
 
@@ -127,7 +133,12 @@ struct StepKernel {
             acc += (vcur[r] - a.shift) * c;
             T res = a.alpha * acc;
             if constexpr (PREV) res -= a.beta * pcur[r];
-            if (pok[r]) __builtin_nontemporal_store(res, &po[pbase + pofs[r]]);  // written once
+            if (pok[r]) {
+                if constexpr (STREAM)
+                    __builtin_nontemporal_store(res, &po[pbase + pofs[r]]);  // written once
+                else
+                    po[pbase + pofs[r]] = res;
+            }
         }
 #pragma unroll
         for (int r = 0; r < RY; ++r)
