@@ -17,7 +17,9 @@
 //  * Lanes run along z (contiguous); each thread owns RY consecutive rows of
 //    y.  It keeps a queue of the 2R+1 values of its points along x in
 //    registers (x-neighbours never touch LDS), and the y-neighbours that fall
-//    on its own rows are read from the queue centres as well.
+//    on its own rows are read from the queue centres as well.  The plane loop
+//    is unrolled over 2(2R+1) planes so that the queue rotates by renaming
+//    registers instead of moving values.
 //  * The current plane of the patch plus a cross-shaped halo (R rows in y, R
 //    columns in z) is staged in LDS, double-buffered with one barrier per
 //    plane; the remaining y- and z-neighbours come from there.  Halo values

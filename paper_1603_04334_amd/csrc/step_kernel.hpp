@@ -92,16 +92,20 @@ struct StepKernel {
     }
 
     // plane x, stage / LDS buffer S; the queue holds planes x-R .. x+R
-    template <int S>
+    // queue slot of logical position d (planes x-R .. x+R) at rotation Q
+    template <int Q>
+    static constexpr int slot(int d) { return (Q + d) % QL; }
+
+    template <int S, int Q>
     __device__ __forceinline__ void plane(int x, Stage (&st)[2], T (*lds)[SY * SZ])
     {
         Stage &s = st[S];
         T *L = lds[S];
 #pragma unroll
-        for (int r = 0; r < RY; ++r) q[r][2 * R] = s.qh[r];
+        for (int r = 0; r < RY; ++r) q[r][slot<Q>(2 * R)] = s.qh[r];
         // publish the centre plane and its halo
 #pragma unroll
-        for (int r = 0; r < RY; ++r) L[(R + lyg * RY + r) * SZ + R + lz] = q[r][R];
+        for (int r = 0; r < RY; ++r) L[(R + lyg * RY + r) * SZ + R + lz] = q[r][slot<Q>(R)];
 #pragma unroll
         for (int i = 0; i < NH; ++i)
             if (hl[i] >= 0) L[hl[i]] = s.h[i];
@@ -121,13 +125,13 @@ struct StepKernel {
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             const int li = (R + lyg * RY + r) * SZ + R + lz;
-            const T c = q[r][R];
+            const T c = q[r][slot<Q>(R)];
             T acc = a.c0 * c;
 #pragma unroll
             for (int p = 1; p <= R; ++p) {
-                const T ym = (r - p >= 0) ? q[r - p][R] : L[li - p * SZ];
-                const T ypl = (r + p < RY) ? q[r + p][R] : L[li + p * SZ];
-                const T six = (q[r][R - p] + q[r][R + p]) + (ym + ypl) + (L[li - p] + L[li + p]);
+                const T ym = (r - p >= 0) ? q[r - p][slot<Q>(R)] : L[li - p * SZ];
+                const T ypl = (r + p < RY) ? q[r + p][slot<Q>(R)] : L[li + p * SZ];
+                const T six = (q[r][slot<Q>(R - p)] + q[r][slot<Q>(R + p)]) + (ym + ypl) + (L[li - p] + L[li + p]);
                 acc += a.cp[p - 1] * six;
             }
             acc += (vcur[r] - a.shift) * c;
@@ -140,10 +144,18 @@ struct StepKernel {
                     po[pbase + pofs[r]] = res;
             }
         }
-#pragma unroll
-        for (int r = 0; r < RY; ++r)
-#pragma unroll
-            for (int d = 0; d < 2 * R; ++d) q[r][d] = q[r][d + 1];
+    }
+
+    // planes x0 .. x0+2*QL-1 (stop at xe): the stage parity and the queue
+    // rotation are compile-time per plane, so the queue never moves
+    template <int U>
+    __device__ __forceinline__ void run_block(int x0, int xe, Stage (&st)[2], T (*lds)[SY * SZ])
+    {
+        if constexpr (U < 2 * QL) {
+            if (x0 + U >= xe) return;
+            plane<U % 2, U % QL>(x0 + U, st, lds);
+            run_block<U + 1>(x0, xe, st, lds);
+        }
     }
 
     static constexpr size_t kLdsBytes = sizeof(T) * 2 * SY * SZ;
@@ -216,12 +228,7 @@ struct StepKernel {
         Stage st[2];
         load_stage(st[0], xs);
         load_stage(st[1], xs + 1);
-        int x = xs;
-        for (; x + 1 < xe; x += 2) {
-            plane<0>(x, st, lds);
-            plane<1>(x + 1, st, lds);
-        }
-        if (x < xe) plane<0>(x, st, lds);
+        for (int x0 = xs; x0 < xe; x0 += 2 * QL) run_block<0>(x0, xe, st, lds);
     }
 };
 
