@@ -151,12 +151,23 @@ __global__ void __launch_bounds__(256) lanczos_3term(double *w, const double *__
 // is orthogonalised against the whole basis when an estimate passes sqrt(eps)
 // and, after that, once more on the next step; its row then restarts at eps1.
 // state[0]: orthogonalise the vector of this step; state[1]: owe the next one.
-__global__ void __launch_bounds__(64) omega_kernel(const double *alpha, const double *beta, int j, double eps1,
-                                                   const double *Wp, const double *Wc, double *Wn, int *state,
-                                                   double *anorm)
+// The kernel first finishes beta_j = sqrt(sum of the wave partials of |w|^2)
+// (the same fixed order as finish_sums) and stores it.
+__global__ void __launch_bounds__(256) omega_kernel(const double *alpha, double *beta, int j, double eps1,
+                                                    const double *Wp, const double *Wc, double *Wn, int *state,
+                                                    double *anorm, const double *partial)
 {
+    __shared__ double red[4];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < kRedWaves; b += 256) v += partial[b];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x >= 64) return;
     const int lane = threadIdx.x;
-    const double aj = alpha[j], bj = beta[j], bjm = j > 0 ? beta[j - 1] : 0.0;
+    const double bj = sqrt((red[0] + red[1]) + (red[2] + red[3]));
+    if (lane == 0) beta[j] = bj;
+    const double aj = alpha[j], bjm = j > 0 ? beta[j - 1] : 0.0;
     const double an = fmax(*anorm, fabs(aj) + bj + bjm);
     double mx = 0.0;
     for (int i = lane; i < j; i += 64) {
@@ -609,14 +620,13 @@ int sparc_lanczos(const sparc_op *op, int32_t k, const double *v0, double *alpha
         hipLaunchKernelGGL(lanczos_3term, rg, tb, 0, s, w, (const double *)vj, (const double *)(vj - (j > 0 ? n : 0)),
                            (const double *)(d_alpha + j), (const double *)(j > 0 ? d_beta + j - 1 : nullptr), n,
                            partial);
-        hipLaunchKernelGGL(finish_sums, dim3(1), tb, 0, s, partial, 1, d_beta + j, nullptr, -1, 1, always);
-        // estimate the loss of orthogonality; when needed, one classical
+        // beta_j and the orthogonality estimates; when needed, one classical
         // Gram-Schmidt pass against v_0 .. v_j and a new beta_j
         const double *Wc = rows + (size_t)(j % 3) * (k + 2);
         const double *Wp = rows + (size_t)((j + 2) % 3) * (k + 2);
         double *Wn = rows + (size_t)((j + 1) % 3) * (k + 2);
-        hipLaunchKernelGGL(omega_kernel, dim3(1), dim3(64), 0, s, (const double *)d_alpha, (const double *)d_beta, j,
-                           eps1, Wp, Wc, Wn, d_state, d_anorm);
+        hipLaunchKernelGGL(omega_kernel, dim3(1), tb, 0, s, (const double *)d_alpha, d_beta, j, eps1, Wp, Wc, Wn,
+                           d_state, d_anorm, (const double *)partial);
         const int nv = j + 1;
         const int *full = d_state;
         hipLaunchKernelGGL(multidot_kernel, rg, tb, 0, s, V, (long long)n, nv, w, n, partial, full);
