@@ -186,8 +186,21 @@ __global__ void __launch_bounds__(kEigThreads) small_sygv_kernel(const double *_
     }
     __syncthreads();
 
-    // 3. cyclic Jacobi, one barrier per round
+    // 3. cyclic Jacobi.  The work split is the same in every round, so each
+    // thread's block (pair k of rows, pair l of columns) and its entries of Z
+    // are fixed once here.
     const int half = np / 2;
+    const bool has_blk = tid < half * half;
+    const int bk = has_blk ? tid / half : 0, bl = has_blk ? tid % half : 0;
+    int zl[2], zi[2];
+    bool zok[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int e = tid + u * kEigThreads;
+        zok[u] = e < half * n;
+        zl[u] = zok[u] ? e / n : 0;
+        zi[u] = zok[u] ? e % n : 0;
+    }
     int cur = 0;
     for (int sweep = 0; sweep < max_sweeps && n > 1; ++sweep) {
         const double(*A)[kEigMax + 1] = CB[cur];
@@ -215,10 +228,9 @@ __global__ void __launch_bounds__(kEigThreads) small_sygv_kernel(const double *_
                 rs[tid] = s;
             }
             __syncthreads();
-            for (int e = tid; e < half * half; e += nt) {
-                const int k = e / half, l = e % half;
-                const int pk = rp[k], qk = rq[k], pl = rp[l], ql = rq[l];
-                const double ck = rc[k], sk = rs[k], cl = rc[l], sl = rs[l];
+            if (has_blk) {
+                const int pk = rp[bk], qk = rq[bk], pl = rp[bl], ql = rq[bl];
+                const double ck = rc[bk], sk = rs[bk], cl = rc[bl], sl = rs[bl];
                 const double a = S[pk][pl], b = S[pk][ql], d = S[qk][pl], g = S[qk][ql];
                 const double a1 = ck * a - sk * d, b1 = ck * b - sk * g;
                 const double d1 = sk * a + ck * d, g1 = sk * b + ck * g;
@@ -227,10 +239,11 @@ __global__ void __launch_bounds__(kEigThreads) small_sygv_kernel(const double *_
                 D[qk][pl] = cl * d1 - sl * g1;
                 D[qk][ql] = sl * d1 + cl * g1;
             }
-            for (int e = tid; e < half * n; e += nt) {
-                const int l = e / n, i = e % n;
-                const int pl = rp[l], ql = rq[l];
-                const double cl = rc[l], sl = rs[l];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (!zok[u]) continue;
+                const int i = zi[u], pl = rp[zl[u]], ql = rq[zl[u]];
+                const double cl = rc[zl[u]], sl = rs[zl[u]];
                 const double za = Z[i][pl], zb = Z[i][ql];
                 Z[i][pl] = cl * za - sl * zb;
                 Z[i][ql] = sl * za + cl * zb;
