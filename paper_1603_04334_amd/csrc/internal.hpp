@@ -132,6 +132,13 @@ int launch_scatter(const sparc_op *op, int dtype, void *out, int64_t ldo, int ns
 int launch_step(const sparc_op *op, int dtype, const void *yk, int64_t ldk, const void *yprev, int64_t ldp,
                 void *out, int64_t ldo, int ns, const StepCoef &c, const StepLaunch &L, hipStream_t stream);
 
+// H applied in FP64 to an FP32 block (values widened on load): the
+// projector gather and the local step of the Rayleigh-Ritz product H Y
+int launch_gather_f32_to_f64(const sparc_op *op, const float *Y, int64_t ldy, int ns, double *part,
+                             hipStream_t stream);
+int launch_step_f32_to_f64(const sparc_op *op, const float *yk, int64_t ldk, double *out, int64_t ldo, int ns,
+                           const StepCoef &c, const StepLaunch &L, hipStream_t stream);
+
 // the full operator step: gather(yk), local step, scatter(alpha)
 int launch_h_step(const sparc_op *op, int dtype, const void *yk, int64_t ldk, const void *yprev, int64_t ldp,
                   void *out, int64_t ldo, int ns, void *part, const StepCoef &c, const StepLaunch &L,

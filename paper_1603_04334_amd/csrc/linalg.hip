@@ -8,8 +8,9 @@
 // are enqueued without host round trips; the tridiagonal T_k is copied back
 // once and its eigenvalues are found on the host by Sturm-sequence bisection.
 //
-// Rayleigh-Ritz (Sec. 3.4, Eq. SubspaceGeneralizedEigenproblem): the block is
-// promoted to FP64, H Y is formed by the fused kernel, H_s = Y^T (H Y) and
+// Rayleigh-Ritz (Sec. 3.4, Eq. SubspaceGeneralizedEigenproblem): an FP32
+// block is widened to FP64 as it is loaded, H Y is formed in FP64 by the
+// fused kernels, H_s = Y^T (H Y) and
 // M_s = Y^T Y are plain FP64 GEMMs (rocBLAS), and the symmetric-definite
 // problem is solved on the device: in one workgroup (Cholesky + Jacobi) for
 // up to 64 columns, by rocSOLVER's dsygvd beyond.
@@ -215,15 +216,6 @@ __global__ void scale_by_inverse(double *dst, const double *src, const double *n
         dst[x] = src[x] * inv;
 }
 
-__global__ void f32_to_f64(const float *src, long long lds, double *dst, long long ldd, long long nd, int ns)
-{
-    const long long total = nd * ns;
-    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total; t += (long long)gridDim.x * blockDim.x) {
-        const long long c = t / nd, x = t - c * nd;
-        dst[c * ldd + x] = (double)src[c * lds + x];
-    }
-}
-
 __global__ void f64_to_f32_dense(const double *src, float *dst, long long n)
 {
     for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x)
@@ -254,7 +246,8 @@ __device__ inline void mfma_f64(double a, double b, double (&acc)[4])
     acc[3] = c[3];
 }
 
-__global__ void __launch_bounds__(256) rr_project_kernel(const double *__restrict__ Y, long long ldy,
+template <typename TY>
+__global__ void __launch_bounds__(256) rr_project_kernel(const TY *__restrict__ Y, long long ldy,
                                                           const double *__restrict__ HY, long long ldh, long long nd,
                                                           int ns, long long kchunk, double *__restrict__ partial)
 {
@@ -270,9 +263,13 @@ __global__ void __launch_bounds__(256) rr_project_kernel(const double *__restric
     const int li = lane & 15, lk = lane >> 4;
     const int kk = tid & 31;
     double accM[2][2][4] = {}, accH[2][2][4] = {};
-    double ra[8], rb[8], rh[8];
+    TY ra[8], rb[8];  // raw values, widened when staged (keeps the loads in flight)
+    double rh[8];
 
-    // thread -> (column c = 8*pass + tid/32, point kk = tid%32 of the slice)
+    // thread -> (column c = 8*pass + tid/32, point kk = tid%32 of the slice).
+    // On a diagonal tile pair both Y panels are the same columns: read and
+    // stage them once.
+    const bool diag = ti == tj;
     auto fetch = [&](long long kb) {
         const long long k = kb + kk;
         const bool kin = k < k1;
@@ -280,8 +277,8 @@ __global__ void __launch_bounds__(256) rr_project_kernel(const double *__restric
         for (int pass = 0; pass < 8; ++pass) {
             const int c = pass * 8 + (tid >> 5);
             const int ca = ti * kRrTile + c, cb = tj * kRrTile + c;
-            ra[pass] = (kin && ca < ns) ? Y[(long long)ca * ldy + k] : 0.0;
-            rb[pass] = (kin && cb < ns) ? Y[(long long)cb * ldy + k] : 0.0;
+            ra[pass] = (kin && ca < ns) ? Y[(long long)ca * ldy + k] : TY(0);
+            if (!diag) rb[pass] = (kin && cb < ns) ? Y[(long long)cb * ldy + k] : TY(0);
             rh[pass] = (kin && cb < ns) ? HY[(long long)cb * ldh + k] : 0.0;
         }
     };
@@ -291,19 +288,20 @@ __global__ void __launch_bounds__(256) rr_project_kernel(const double *__restric
 #pragma unroll
         for (int pass = 0; pass < 8; ++pass) {
             const int c = pass * 8 + (tid >> 5);
-            sA[c][kk] = ra[pass];
-            sB[c][kk] = rb[pass];
+            sA[c][kk] = (double)ra[pass];
+            if (!diag) sB[c][kk] = (double)rb[pass];
             sH[c][kk] = rh[pass];
         }
         __syncthreads();
         if (kb + kRrK < k1) fetch(kb + kRrK);
+        const double(*SB)[kRrK + 1] = diag ? sA : sB;
 #pragma unroll
         for (int ks = 0; ks < kRrK; ks += 4) {
             double a[2], b[2], h[2];
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 a[u] = sA[wi + 16 * u + li][ks + lk];
-                b[u] = sB[wj + 16 * u + li][ks + lk];
+                b[u] = SB[wj + 16 * u + li][ks + lk];
                 h[u] = sH[wj + 16 * u + li][ks + lk];
             }
 #pragma unroll
@@ -665,7 +663,6 @@ size_t sparc_rr_workspace_bytes(const sparc_op *op, int32_t dtype, int32_t ns)
 {
     if (!op || ns < 1) return 0;
     size_t b = 0;
-    if (dtype == SPARC_F32) b += align_up((size_t)op->nd * ns * sizeof(double));  // promoted Y
     b += align_up((size_t)op->nd * ns * sizeof(double));                           // H Y
     b += gather_bytes(op, SPARC_F64, ns);                                           // gathered projections
     b += 2 * align_up((size_t)ns * ns * sizeof(double));                           // H_s, M_s
@@ -686,15 +683,6 @@ int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_
     hipStream_t s = (hipStream_t)stream;
     const long long nd = op->nd;
     char *p = (char *)ws;
-    const double *Y64 = (const double *)Y;
-    long long ld64 = ldy;
-    if (dtype == SPARC_F32) {
-        double *y = (double *)p;
-        p += align_up((size_t)nd * ns * sizeof(double));
-        hipLaunchKernelGGL(f32_to_f64, stream_grid(nd * ns), dim3(256), 0, s, (const float *)Y, (long long)ldy, y, nd, nd, ns);
-        Y64 = y;
-        ld64 = nd;
-    }
     double *HY = (double *)p;
     p += align_up((size_t)nd * ns * sizeof(double));
     double *G = (double *)p;
@@ -714,12 +702,23 @@ int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_
     int st;
     StepLaunch L = choose_step_launch(op, SPARC_F64, ns);
     StepCoef hc{1.0, 0.0, 0.0, 0};
-    if ((st = launch_h_step(op, SPARC_F64, Y64, ld64, nullptr, 0, HY, nd, ns, G, hc, L, s))) return st;
-
     const long long kc = rr_chunk(nd, ns);
     const int nch = (int)((nd + kc - 1) / kc);
     const int nt = (ns + kRrTile - 1) / kRrTile;
-    hipLaunchKernelGGL(rr_project_kernel, dim3(nch, nt, nt), dim3(256), 0, s, Y64, ld64, HY, nd, nd, ns, kc, partial);
+    const dim3 pg(nch, nt, nt);
+    if (dtype == SPARC_F64) {
+        if ((st = launch_h_step(op, SPARC_F64, Y, ldy, nullptr, 0, HY, nd, ns, G, hc, L, s))) return st;
+        hipLaunchKernelGGL(rr_project_kernel<double>, pg, dim3(256), 0, s, (const double *)Y, (long long)ldy,
+                           (const double *)HY, nd, nd, ns, kc, partial);
+    } else {
+        // H in FP64 on the FP32 values, widened as they are loaded
+        const float *Yf = (const float *)Y;
+        if ((st = launch_gather_f32_to_f64(op, Yf, ldy, ns, G, s))) return st;
+        if ((st = launch_step_f32_to_f64(op, Yf, ldy, HY, nd, ns, hc, L, s))) return st;
+        if ((st = launch_scatter(op, SPARC_F64, HY, nd, ns, G, 1.0, s))) return st;
+        hipLaunchKernelGGL(rr_project_kernel<float>, pg, dim3(256), 0, s, Yf, (long long)ldy, (const double *)HY, nd,
+                           nd, ns, kc, partial);
+    }
     const long long tot = 2LL * ns * ns;
     hipLaunchKernelGGL(rr_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, partial, nch, ns, Ms, Hs);
     dim3 tb(16, 16), tg((ns + 15) / 16, (ns + 15) / 16);

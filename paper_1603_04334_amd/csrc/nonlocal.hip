@@ -26,11 +26,11 @@
 
 namespace sparc {
 
-template <typename T>
-__global__ void __launch_bounds__(256) gather_kernel(const GatherArgs<T> g)
+template <typename T, typename TI>
+__global__ void __launch_bounds__(256) gather_kernel(const GatherArgs<T, TI> g)
 {
     __shared__ T tile[4][16][16];
-    gather_item<T>(g, blockIdx.x, blockIdx.y, blockIdx.z, tile);
+    gather_item<T, TI>(g, blockIdx.x, blockIdx.y, blockIdx.z, tile);
 }
 
 template <typename T>
@@ -40,12 +40,12 @@ __global__ void __launch_bounds__(256) scatter_kernel(const ScatterArgs<T> s)
     scatter_item<T>(s, blockIdx.x, blockIdx.y, gl);
 }
 
-template <typename T>
+template <typename T, typename TI = T>
 static int launch_gather_t(const sparc_op *op, const void *Y, int64_t ldy, int ns, void *part, hipStream_t stream,
                            const T *chi)
 {
-    GatherArgs<T> a;
-    a.Y = (const T *)Y;
+    GatherArgs<T, TI> a;
+    a.Y = (const TI *)Y;
     a.ldy = ldy;
     a.ns = ns;
     a.nproj_total = op->nproj_total;
@@ -55,9 +55,16 @@ static int launch_gather_t(const sparc_op *op, const void *Y, int64_t ldy, int n
     a.part = (T *)part;
     dim3 grid(op->natoms, (ns + 15) / 16, kGatherSplit);
     ProfScope prof(1, stream);
-    hipLaunchKernelGGL(gather_kernel<T>, grid, dim3(256), 0, stream, a);
+    hipLaunchKernelGGL((gather_kernel<T, TI>), grid, dim3(256), 0, stream, a);
     SPARC_HIP(hipGetLastError());
     return SPARC_OK;
+}
+
+int launch_gather_f32_to_f64(const sparc_op *op, const float *Y, int64_t ldy, int ns, double *part, hipStream_t stream)
+{
+    if (op->natoms == 0) return SPARC_OK;
+    if ((long long)(ns + 15) / 16 > 65535) return fail(SPARC_E_SHAPE, "too many columns for one gather launch");
+    return launch_gather_t<double, float>(op, Y, ldy, ns, part, stream, op->d_chi64);
 }
 
 int launch_gather(const sparc_op *op, int dtype, const void *Y, int64_t ldy, int ns, void *part, hipStream_t stream)

@@ -6,9 +6,10 @@
 
 namespace sparc {
 
-template <typename T>
+// TI: storage type of Y (FP32 blocks may be projected in FP64)
+template <typename T, typename TI = T>
 struct GatherArgs {
-    const T *Y;
+    const TI *Y;
     long long ldy;
     int ns;
     int nproj_total;
@@ -52,8 +53,8 @@ __device__ inline int acc_row(int lane, int r)
 
 constexpr int kGatherUnroll = 8;  // groups of 4 points per wave per batch
 
-template <typename T>
-__device__ __forceinline__ void gather_item(const GatherArgs<T> &g, int atom, int cb, int ks, T (*tile)[16][16])
+template <typename T, typename TI = T>
+__device__ __forceinline__ void gather_item(const GatherArgs<T, TI> &g, int atom, int cb, int ks, T (*tile)[16][16])
 {
     const int c0 = cb * 16;
     const AtomDev A = g.atoms[atom];
@@ -68,7 +69,7 @@ __device__ __forceinline__ void gather_item(const GatherArgs<T> &g, int atom, in
     const int col = c0 + i;
     const bool col_ok = col < g.ns;
     const bool proj_ok = i < A.nproj;
-    const T *y = g.Y + (long long)(col_ok ? col : 0) * g.ldy;
+    const TI *y = g.Y + (long long)(col_ok ? col : 0) * g.ldy;
     const T *ch = g.chi + A.chi0 + (long long)(proj_ok ? i : 0) * nbox;
     const int *boff = g.box_off + A.box0;
 
@@ -86,7 +87,7 @@ __device__ __forceinline__ void gather_item(const GatherArgs<T> &g, int atom, in
         for (int u = 0; u < kGatherUnroll; ++u) {
             const int pt = base + 4 * u + k;
             const bool ok = pt < k1;
-            const T yv = y[off[u]];
+            const T yv = (T)y[off[u]];
             const T cv = ch[ok ? pt : k0];
             av[u] = (ok && col_ok) ? yv : T(0);
             bv[u] = (ok && proj_ok) ? cv : T(0);

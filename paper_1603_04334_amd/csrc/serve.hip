@@ -132,7 +132,7 @@ size_t estimate_footprint(const Cluster &c, int lanczos_k)
     const size_t nd = (size_t)c.nd, ns = (size_t)c.ns;
     size_t f = nd * 12 + chi * 12 + box * 28 + 4096;                 // operator
     f += 3 * nd * ns * s + 4 * std::max<size_t>(1, nproj) * ns * s;  // X, Y, filter workspace
-    f += (c.dtype == SPARC_F32 ? nd * ns * 8 : 0) + nd * ns * 8;      // Rayleigh-Ritz blocks
+    f += nd * ns * 8;                                                 // Rayleigh-Ritz H Y
     f += 4 * std::max<size_t>(1, nproj) * ns * 8 + 1024 * 2 * ns * ns * 8 + 4 * (ns + 64) * (ns + 64) * 8 + 4096;
     // first request only: Lanczos, and for FP32 the FP64 blocks of the first pass
     size_t first = nd * (lanczos_k + 1) * 8 + 4096 * (lanczos_k + 2) * 8;

@@ -34,6 +34,8 @@
 //    yprev and out are streamed with non-temporal loads and stores, so the
 //    L2 keeps the values that are reused (halos of Y_k, V_eff) instead;
 //    smaller blocks stay cached from one step to the next.
+#include <type_traits>
+
 #include "step_kernel.hpp"
 
 namespace sparc {
@@ -41,10 +43,10 @@ namespace sparc {
 const TileShape kShapes[kNumShapes] = {{32, 2, 256}, {32, 2, 512}, {32, 2, 768}, {64, 2, 256},
                                        {64, 2, 512}, {32, 4, 256}};
 
-template <typename T, int TZ, int RY, int NT, bool PREV, bool STREAM>
-__global__ void __launch_bounds__(NT) step_kernel(const StepArgs<T> a)
+template <typename T, int TZ, int RY, int NT, bool PREV, bool STREAM, typename TI>
+__global__ void __launch_bounds__(NT) step_kernel(const StepArgs<T, TI> a)
 {
-    using K = StepKernel<T, TZ, RY, NT, PREV, STREAM>;
+    using K = StepKernel<T, TZ, RY, NT, PREV, STREAM, TI>;
     __shared__ T lds[2][K::SY * K::SZ];
     K k(a);
     k.run(blockIdx.x, lds);
@@ -69,30 +71,34 @@ StepLaunch choose_step_launch(const sparc_op *op, int dtype, int ns)
     return L;
 }
 
-template <typename T, int TZ, int RY, int NT>
-static int launch_typed(const StepArgs<T> &a, bool prev, bool strm, hipStream_t stream)
+template <typename T, int TZ, int RY, int NT, typename TI>
+static int launch_typed(const StepArgs<T, TI> &a, bool prev, bool strm, hipStream_t stream)
 {
     const dim3 g(a.nblocks), b(NT);
-    if (prev && strm)
-        hipLaunchKernelGGL((step_kernel<T, TZ, RY, NT, true, true>), g, b, 0, stream, a);
-    else if (prev)
-        hipLaunchKernelGGL((step_kernel<T, TZ, RY, NT, true, false>), g, b, 0, stream, a);
-    else if (strm)
-        hipLaunchKernelGGL((step_kernel<T, TZ, RY, NT, false, true>), g, b, 0, stream, a);
-    else
-        hipLaunchKernelGGL((step_kernel<T, TZ, RY, NT, false, false>), g, b, 0, stream, a);
+    if constexpr (std::is_same<T, TI>::value) {
+        if (prev && strm)
+            hipLaunchKernelGGL((step_kernel<T, TZ, RY, NT, true, true, TI>), g, b, 0, stream, a);
+        else if (prev)
+            hipLaunchKernelGGL((step_kernel<T, TZ, RY, NT, true, false, TI>), g, b, 0, stream, a);
+    }
+    if (!prev) {
+        if (strm)
+            hipLaunchKernelGGL((step_kernel<T, TZ, RY, NT, false, true, TI>), g, b, 0, stream, a);
+        else
+            hipLaunchKernelGGL((step_kernel<T, TZ, RY, NT, false, false, TI>), g, b, 0, stream, a);
+    }
     SPARC_HIP(hipGetLastError());
     return SPARC_OK;
 }
 
-template <typename T>
+template <typename T, typename TI = T>
 static int launch_step_t(const sparc_op *op, const void *yk, int64_t ldk, const void *yprev, int64_t ldp,
                          void *out, int64_t ldo, int ns, const StepCoef &c, const StepLaunch &L,
                          hipStream_t stream, const T *veff)
 {
     const TileShape &s = kShapes[L.shape];
-    StepArgs<T> a;
-    a.yk = (const T *)yk;
+    StepArgs<T, TI> a;
+    a.yk = (const TI *)yk;
     a.yprev = (const T *)yprev;
     a.out = (T *)out;
     a.veff = veff;
@@ -117,17 +123,24 @@ static int launch_step_t(const sparc_op *op, const void *yk, int64_t ldk, const 
     a.beta = (T)c.beta;
     a.shift = (T)c.shift;
     // blocks the last-level cache cannot keep between steps are streamed
-    const bool strm = 3.0 * (double)op->nd * ns * sizeof(T) > kStreamBytes;
+    const bool strm = (double)op->nd * ns * (2 * sizeof(T) + sizeof(TI)) > kStreamBytes;
     ProfScope prof(prev ? 0 : 3, stream);
     switch (L.shape) {
-        case 0: return launch_typed<T, 32, 2, 256>(a, prev, strm, stream);
-        case 1: return launch_typed<T, 32, 2, 512>(a, prev, strm, stream);
-        case 2: return launch_typed<T, 32, 2, 768>(a, prev, strm, stream);
-        case 3: return launch_typed<T, 64, 2, 256>(a, prev, strm, stream);
-        case 4: return launch_typed<T, 64, 2, 512>(a, prev, strm, stream);
-        case 5: return launch_typed<T, 32, 4, 256>(a, prev, strm, stream);
+        case 0: return launch_typed<T, 32, 2, 256, TI>(a, prev, strm, stream);
+        case 1: return launch_typed<T, 32, 2, 512, TI>(a, prev, strm, stream);
+        case 2: return launch_typed<T, 32, 2, 768, TI>(a, prev, strm, stream);
+        case 3: return launch_typed<T, 64, 2, 256, TI>(a, prev, strm, stream);
+        case 4: return launch_typed<T, 64, 2, 512, TI>(a, prev, strm, stream);
+        case 5: return launch_typed<T, 32, 4, 256, TI>(a, prev, strm, stream);
     }
     return fail(SPARC_E_ARG, "unknown tile shape");
+}
+
+int launch_step_f32_to_f64(const sparc_op *op, const float *yk, int64_t ldk, double *out, int64_t ldo, int ns,
+                           const StepCoef &c, const StepLaunch &L, hipStream_t stream)
+{
+    if (c.has_prev) return fail(SPARC_E_ARG, "mixed-precision step has no Y_{k-1} term");
+    return launch_step_t<double, float>(op, yk, ldk, nullptr, 0, out, ldo, ns, c, L, stream, op->d_veff64);
 }
 
 int launch_step(const sparc_op *op, int dtype, const void *yk, int64_t ldk, const void *yprev, int64_t ldp,

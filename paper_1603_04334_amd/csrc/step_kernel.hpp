@@ -7,9 +7,10 @@
 
 namespace sparc {
 
-template <typename T>
+// TI: storage type of Y_k (FP32 blocks may feed an FP64 application of H)
+template <typename T, typename TI = T>
 struct StepArgs {
-    const T *yk;
+    const TI *yk;
     const T *yprev;
     T *out;
     const T *veff;
@@ -24,7 +25,7 @@ struct StepArgs {
 };
 
 // STREAM: Y_{k-1} and the output bypass the caches (non-temporal accesses)
-template <typename T, int TZ, int RY, int NT, bool PREV, bool STREAM = false>
+template <typename T, int TZ, int RY, int NT, bool PREV, bool STREAM = false, typename TI = T>
 struct StepKernel {
     static constexpr int R = kMaxRadius;
     static constexpr int QL = 2 * R + 1;     // queue length: planes x-R .. x+R
@@ -44,8 +45,8 @@ struct StepKernel {
         T p[RY];
     };
 
-    const StepArgs<T> &a;
-    const T *yk;
+    const StepArgs<T, TI> &a;
+    const TI *yk;
     const T *yp;
     T *out;
     long long P;
@@ -57,7 +58,7 @@ struct StepKernel {
     int hl[NH];
     T q[RY][QL];
 
-    __device__ StepKernel(const StepArgs<T> &args) : a(args) {}
+    __device__ StepKernel(const StepArgs<T, TI> &args) : a(args) {}
 
     __device__ __forceinline__ void load_stage(Stage &s, int t) const
     {
@@ -66,7 +67,7 @@ struct StepKernel {
 #pragma unroll
         for (int i = 0; i < NH; ++i) {
             const bool ok = tin && hok[i];
-            const T v = yk[base + (ok ? hofs[i] : 0)];
+            const T v = (T)yk[base + (ok ? hofs[i] : 0)];
             s.h[i] = ok ? v : T(0);
         }
         const int th = t + R;
@@ -75,7 +76,7 @@ struct StepKernel {
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             const bool ok = hin && pok[r];
-            const T v = yk[hbase + (ok ? pofs[r] : 0)];
+            const T v = (T)yk[hbase + (ok ? pofs[r] : 0)];
             s.qh[r] = ok ? v : T(0);
         }
 #pragma unroll
@@ -221,7 +222,7 @@ struct StepKernel {
 #pragma unroll
             for (int r = 0; r < RY; ++r) {
                 const bool ok = in && pok[r];
-                const T v = yk[(long long)(ok ? xx : 0) * P + (ok ? pofs[r] : 0)];
+                const T v = (T)yk[(long long)(ok ? xx : 0) * P + (ok ? pofs[r] : 0)];
                 q[r][d] = ok ? v : T(0);
             }
         }
