@@ -2,18 +2,20 @@
 //
 // Lanczos (Sec. 4: extremal eigenvalues of H by a few Lanczos iterations)
 // runs entirely on the device: H v through the fused step kernel, then
-// deterministic two-pass reductions for the inner products (per-block partial
-// sums, then one fixed-order sum), and full re-orthogonalisation against the
-// stored basis.  The scalars stay on the device between steps, so the k steps
-// are enqueued without host round trips; the tridiagonal T_k is copied back
-// once and its eigenvalues are found on the host by Sturm-sequence bisection.
+// deterministic two-pass reductions for the inner products (one partial per
+// block, then one fixed-order sum, finished by whichever kernel needs the
+// value), and partial re-orthogonalisation against the stored basis, decided
+// on the device by the omega recurrence.  The scalars stay on the device
+// between steps, so the k steps are enqueued without host round trips; the
+// tridiagonal T_k is copied back once and its eigenvalues are found on the
+// host by Sturm-sequence bisection.
 //
-// Rayleigh-Ritz (Sec. 3.4, Eq. SubspaceGeneralizedEigenproblem): an FP32
-// block is widened to FP64 as it is loaded, H Y is formed in FP64 by the
-// fused kernels, H_s = Y^T (H Y) and
-// M_s = Y^T Y are plain FP64 GEMMs (rocBLAS), and the symmetric-definite
-// problem is solved on the device: in one workgroup (Cholesky + Jacobi) for
-// up to 64 columns, by rocSOLVER's dsygvd beyond.
+// Rayleigh-Ritz (Sec. 3.4, Eq. SubspaceGeneralizedEigenproblem): H Y is
+// formed in FP64 by the fused kernels (an FP32 block is widened as it is
+// loaded), H_s = Y^T (H Y) and M_s = Y^T Y come from one FP64 matrix-core
+// kernel, and the symmetric-definite problem is solved on the device: in one
+// workgroup (Cholesky + Jacobi) for up to 64 columns, by rocSOLVER's dsygvd
+// beyond.
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -26,9 +28,9 @@
 
 namespace sparc {
 
-constexpr int kRedBlocks = 1024;          // blocks of the first reduction pass
-constexpr int kRedWaves = kRedBlocks * 4;  // one partial per wave
-constexpr int kDotGroup = 8;              // vectors per pass over a wave's segment
+constexpr int kRedBlocks = 1024;  // blocks of the first reduction pass: one partial per block
+constexpr int kDotGroup = 8;      // vectors per pass over a block's segment
+constexpr int kUnroll = 4;        // points per thread with loads in flight together
 
 __device__ inline double wave_sum(double v)
 {
@@ -36,111 +38,173 @@ __device__ inline double wave_sum(double v)
     return v;
 }
 
-// wave-level partial inner products: partial[gw*(nv+1) + i] = sum over wave
-// gw's points of V_i(x) w(x) for i < nv, and of w(x)^2 for i = nv.  Each wave
-// owns a contiguous segment of the vectors; groups of 8 vectors per pass.
-// (run != nullptr and *run == 0: nothing to do)
+// sum over the 4 waves of a 256-thread block, the same value in every thread
+__device__ inline double block_sum(double v, double *red)
+{
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const double t = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return t;
+}
+
+// sum of entry i of the kRedBlocks block partials (stride per block) in one
+// fixed order, so that every block that needs the value finishes it
+// bitwise identically
+__device__ inline double sum_partials(const double *partial, int stride, int i, double *red)
+{
+    double v = 0.0;
+#pragma unroll
+    for (int u = 0; u < kRedBlocks / 256; ++u) v += partial[(long long)(threadIdx.x + 256 * u) * stride + i];
+    return block_sum(v, red);
+}
+
+// the contiguous segment of n points owned by block b of a reduction pass
+__device__ inline void block_segment(long long n, long long &beg, long long &end)
+{
+    const long long seg = ((n + kRedBlocks - 1) / kRedBlocks + 63) / 64 * 64;
+    beg = blockIdx.x * seg;
+    end = (beg + seg < n) ? beg + seg : n;
+}
+
+// block-level partial inner products: partial[b*(nv+1) + i] = sum over block
+// b's points of V_i(x) w(x) for i < nv, and of w(x)^2 for i = nv.  Groups of
+// 8 vectors per pass over the segment.  (run != nullptr and *run == 0:
+// nothing to do)
 __global__ void __launch_bounds__(256) multidot_kernel(const double *__restrict__ V, long long ldv, int nv,
                                                        const double *__restrict__ w, long long n,
                                                        double *__restrict__ partial, const int *run)
 {
     if (run && !*run) return;
-    const int lane = threadIdx.x & 63;
-    const long long gw = blockIdx.x * 4LL + (threadIdx.x >> 6);
-    const long long nw = gridDim.x * 4LL;
-    const long long seg = ((n + nw - 1) / nw + 63) / 64 * 64;
-    const long long beg = gw * seg;
-    const long long end = (beg + seg < n) ? beg + seg : n;
-    double *out = partial + gw * (nv + 1);
+    __shared__ double red[4];
+    long long beg, end;
+    block_segment(n, beg, end);
+    double *out = partial + (long long)blockIdx.x * (nv + 1);
     for (int i0 = 0; i0 <= nv; i0 += kDotGroup) {
         double acc[kDotGroup];
 #pragma unroll
         for (int u = 0; u < kDotGroup; ++u) acc[u] = 0.0;
-        for (long long x = beg + lane; x < end; x += 64) {
-            const double wx = w[x];
+        for (long long x0 = beg + threadIdx.x; x0 < end; x0 += 256 * kUnroll) {
+            double wx[kUnroll];
+#pragma unroll
+            for (int r = 0; r < kUnroll; ++r) {
+                const long long x = x0 + 256 * r;
+                wx[r] = x < end ? w[x] : 0.0;
+            }
 #pragma unroll
             for (int u = 0; u < kDotGroup; ++u) {
                 const int i = i0 + u;
-                const double vx = (i < nv) ? V[(long long)i * ldv + x] : wx;
-                acc[u] += (i <= nv) ? vx * wx : 0.0;
+                if (i > nv) break;
+                double vx[kUnroll];
+#pragma unroll
+                for (int r = 0; r < kUnroll; ++r) {
+                    const long long x = x0 + 256 * r;
+                    vx[r] = (i == nv) ? wx[r] : (x < end ? V[(long long)i * ldv + x] : 0.0);
+                }
+#pragma unroll
+                for (int r = 0; r < kUnroll; ++r) acc[u] += vx[r] * wx[r];
             }
         }
 #pragma unroll
         for (int u = 0; u < kDotGroup; ++u) {
-            const double t = wave_sum(acc[u]);
-            if (lane == 0 && i0 + u <= nv) out[i0 + u] = t;
+            const double t = block_sum(acc[u], red);
+            if (threadIdx.x == 0 && i0 + u <= nv) out[i0 + u] = t;
         }
     }
 }
 
-// out[i] = sum over the kRedWaves wave partials of entry i (stride per wave),
-// one block per i, fixed tree order.  alpha_out[0] = out[alpha_index] if set;
-// mode 1 stores the square root.
+// out[i] = sum over the block partials of entry i (stride per block), one
+// block per i.  alpha_out[0] = out[alpha_index] if set; mode 1 stores the
+// square root.
 __global__ void __launch_bounds__(256) finish_sums(const double *partial, int stride, double *out,
                                                    double *alpha_out, int alpha_index, int mode, const int *run)
 {
     if (run && !*run) return;
     __shared__ double red[4];
     const int i = blockIdx.x;
-    double v = 0.0;
-    for (int b = threadIdx.x; b < kRedWaves; b += 256) v += partial[(long long)b * stride + i];
-    v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
+    const double t = sum_partials(partial, stride, i, red);
     if (threadIdx.x == 0) {
-        const double t = (red[0] + red[1]) + (red[2] + red[3]);
         out[i] = mode == 1 ? sqrt(t) : t;
         if (alpha_out && i == alpha_index) alpha_out[0] = t;
     }
 }
 
-// w -= sum_i coeff[i] V_i, and partial[gw] = sum over wave gw's points of the new w^2
+// w -= sum_i coeff[i] V_i, and partial[b] = sum over block b's points of the new w^2
 __global__ void __launch_bounds__(256) orth_apply_norm(double *w, const double *__restrict__ V, long long ldv, int nv,
                                                        const double *__restrict__ coeff, long long n,
                                                        double *__restrict__ partial, const int *run)
 {
     if (run && !*run) return;
-    const int lane = threadIdx.x & 63;
-    const long long gw = blockIdx.x * 4LL + (threadIdx.x >> 6);
-    const long long nw = gridDim.x * 4LL;
-    const long long seg = ((n + nw - 1) / nw + 63) / 64 * 64;
-    const long long beg = gw * seg;
-    const long long end = (beg + seg < n) ? beg + seg : n;
+    __shared__ double red[4];
+    long long beg, end;
+    block_segment(n, beg, end);
     double nrm = 0.0;
-    for (long long x = beg + lane; x < end; x += 64) {
-        double s = 0.0;
-#pragma unroll 8
-        for (int i = 0; i < nv; ++i) s += coeff[i] * V[(long long)i * ldv + x];
-        const double r = w[x] - s;
-        w[x] = r;
-        nrm += r * r;
+    for (long long x0 = beg + threadIdx.x; x0 < end; x0 += 256 * kUnroll) {
+        double s[kUnroll];
+#pragma unroll
+        for (int r = 0; r < kUnroll; ++r) s[r] = 0.0;
+        for (int i = 0; i < nv; ++i) {
+            const double c = coeff[i];
+#pragma unroll
+            for (int r = 0; r < kUnroll; ++r) {
+                const long long x = x0 + 256 * r;
+                s[r] += c * (x < end ? V[(long long)i * ldv + x] : 0.0);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kUnroll; ++r) {
+            const long long x = x0 + 256 * r;
+            if (x < end) {
+                const double v = w[x] - s[r];
+                w[x] = v;
+                nrm += v * v;
+            }
+        }
     }
-    nrm = wave_sum(nrm);
-    if (lane == 0) partial[gw] = nrm;
+    const double t = block_sum(nrm, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// three-term Lanczos step: w -= alpha_j v_j + beta_{j-1} v_{j-1} (bprev may be
-// null at j = 0); partial[gw] = sum over wave gw's points of the new w^2
+// three-term Lanczos step.  alpha_j = v_j^T w is first finished from the block
+// partials of the inner-product pass (entry 0 of stride 2; block 0 stores it),
+// then w -= alpha_j v_j + beta_{j-1} v_{j-1} (bprev may be null at j = 0) and
+// partial[b] = sum over block b's points of the new w^2
 __global__ void __launch_bounds__(256) lanczos_3term(double *w, const double *__restrict__ vj,
-                                                     const double *__restrict__ vjm, const double *alpha,
-                                                     const double *bprev, long long n, double *__restrict__ partial)
+                                                     const double *__restrict__ vjm, const double *apart,
+                                                     double *alpha, const double *bprev, long long n,
+                                                     double *__restrict__ partial)
 {
-    const int lane = threadIdx.x & 63;
-    const long long gw = blockIdx.x * 4LL + (threadIdx.x >> 6);
-    const long long nw = gridDim.x * 4LL;
-    const long long seg = ((n + nw - 1) / nw + 63) / 64 * 64;
-    const long long beg = gw * seg;
-    const long long end = (beg + seg < n) ? beg + seg : n;
-    const double a = *alpha, b = bprev ? *bprev : 0.0;
+    __shared__ double red[4];
+    const double a = sum_partials(apart, 2, 0, red);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *alpha = a;
+    const double b = bprev ? *bprev : 0.0;
     const double *vm = bprev ? vjm : vj;
+    long long beg, end;
+    block_segment(n, beg, end);
     double nrm = 0.0;
-    for (long long x = beg + lane; x < end; x += 64) {
-        const double r = w[x] - (a * vj[x] + b * vm[x]);
-        w[x] = r;
-        nrm += r * r;
+    for (long long x0 = beg + threadIdx.x; x0 < end; x0 += 256 * kUnroll) {
+        double wv[kUnroll], v1[kUnroll], v2[kUnroll];
+#pragma unroll
+        for (int r = 0; r < kUnroll; ++r) {
+            const long long x = x0 + 256 * r;
+            const bool ok = x < end;
+            wv[r] = ok ? w[x] : 0.0;
+            v1[r] = ok ? vj[x] : 0.0;
+            v2[r] = ok ? vm[x] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < kUnroll; ++r) {
+            const long long x = x0 + 256 * r;
+            if (x < end) {
+                const double v = wv[r] - (a * v1[r] + b * v2[r]);
+                w[x] = v;
+                nrm += v * v;
+            }
+        }
     }
-    nrm = wave_sum(nrm);
-    if (lane == 0) partial[gw] = nrm;
+    const double t = block_sum(nrm, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
 // Partial reorthogonalisation (Simon's omega recurrence).  Row j of the
@@ -152,21 +216,16 @@ __global__ void __launch_bounds__(256) lanczos_3term(double *w, const double *__
 // is orthogonalised against the whole basis when an estimate passes sqrt(eps)
 // and, after that, once more on the next step; its row then restarts at eps1.
 // state[0]: orthogonalise the vector of this step; state[1]: owe the next one.
-// The kernel first finishes beta_j = sqrt(sum of the wave partials of |w|^2)
+// The kernel first finishes beta_j = sqrt(sum of the block partials of |w|^2)
 // (the same fixed order as finish_sums) and stores it.
 __global__ void __launch_bounds__(256) omega_kernel(const double *alpha, double *beta, int j, double eps1,
                                                     const double *Wp, const double *Wc, double *Wn, int *state,
                                                     double *anorm, const double *partial)
 {
     __shared__ double red[4];
-    double v = 0.0;
-    for (int b = threadIdx.x; b < kRedWaves; b += 256) v += partial[b];
-    v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
+    const double bj = sqrt(sum_partials(partial, 1, 0, red));
     if (threadIdx.x >= 64) return;
     const int lane = threadIdx.x;
-    const double bj = sqrt((red[0] + red[1]) + (red[2] + red[3]));
     if (lane == 0) beta[j] = bj;
     const double aj = alpha[j], bjm = j > 0 ? beta[j - 1] : 0.0;
     const double an = fmax(*anorm, fabs(aj) + bj + bjm);
@@ -208,12 +267,36 @@ __global__ void omega_init(double *rows, int len, int *state, double *anorm)
     }
 }
 
-// dst = src / *norm
-__global__ void scale_by_inverse(double *dst, const double *src, const double *norm, long long n)
+// dst = src / nrm.  When redo is null or *redo is set, nrm = sqrt(sum of the
+// block partials of |src|^2) is finished here (block 0 stores it in *norm);
+// otherwise nrm = *norm.  One 256-thread block per reduction segment.
+__global__ void __launch_bounds__(256) scale_by_norm(double *dst, const double *__restrict__ src, double *norm,
+                                                     const double *partial, const int *redo, long long n)
 {
-    const double inv = 1.0 / *norm;
-    for (long long x = blockIdx.x * (long long)blockDim.x + threadIdx.x; x < n; x += (long long)gridDim.x * blockDim.x)
-        dst[x] = src[x] * inv;
+    __shared__ double red[4];
+    double nrm;
+    if (!redo || *redo) {
+        nrm = sqrt(sum_partials(partial, 1, 0, red));
+        if (blockIdx.x == 0 && threadIdx.x == 0) *norm = nrm;
+    } else {
+        nrm = *norm;
+    }
+    const double inv = 1.0 / nrm;
+    long long beg, end;
+    block_segment(n, beg, end);
+    for (long long x0 = beg + threadIdx.x; x0 < end; x0 += 256 * kUnroll) {
+        double v[kUnroll];
+#pragma unroll
+        for (int r = 0; r < kUnroll; ++r) {
+            const long long x = x0 + 256 * r;
+            v[r] = x < end ? src[x] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < kUnroll; ++r) {
+            const long long x = x0 + 256 * r;
+            if (x < end) dst[x] = v[r] * inv;
+        }
+    }
 }
 
 __global__ void f64_to_f32_dense(const double *src, float *dst, long long n)
@@ -556,18 +639,18 @@ size_t sparc_lanczos_workspace_bytes(const sparc_op *op, int32_t k)
     size_t b = align_up((size_t)op->nd * (k + 1) * sizeof(double));  // basis V_0..V_{k-1} and w
     b += gather_bytes(op, SPARC_F64, 1);                                  // gathered projections
     b += align_up((size_t)(4 * k + 8) * sizeof(double));                  // alpha, beta, coeff, norm
-    b += align_up((size_t)kRedWaves * (k + 2) * sizeof(double));          // partial sums
+    b += align_up((size_t)kRedBlocks * (k + 3) * sizeof(double));         // block partial sums
     b += align_up((size_t)(3 * (k + 2) + 1) * sizeof(double));            // omega rows, ||T|| estimate
     b += align_up(2 * sizeof(int));                                         // reorthogonalisation state
     return b;
 }
 
-// Lanczos with full re-orthogonalisation, one classical Gram-Schmidt pass per
-// step against the whole basis: w = H v_j, c = [v_0..v_j]^T w,
-// w -= [v_0..v_j] c, beta_j = |w|, v_{j+1} = w / beta_j, and alpha_j = c_j.
-// In exact arithmetic c_i = 0 for i < j-1 and c_{j-1} = beta_{j-1}, so this is
-// the three-term Lanczos recurrence with the rounding-induced components along
-// older vectors removed at every step.
+// Lanczos with partial re-orthogonalisation: w = H v_j, alpha_j = v_j^T w,
+// w -= alpha_j v_j + beta_{j-1} v_{j-1}, beta_j = |w|; when the omega
+// recurrence (omega_kernel) estimates a loss of orthogonality beyond sqrt(eps),
+// one classical Gram-Schmidt pass against v_0 .. v_j (c = V^T w, w -= V c) and
+// a new beta_j; v_{j+1} = w / beta_j.  Every step is enqueued without a host
+// round trip: the conditional pass reads its flag on the device.
 int sparc_lanczos(const sparc_op *op, int32_t k, const double *v0, double *alpha, double *beta, double *theta,
                   void *ws, size_t ws_bytes, void *stream)
 {
@@ -587,8 +670,9 @@ int sparc_lanczos(const sparc_op *op, int32_t k, const double *v0, double *alpha
     double *d_coeff = d_beta + k;       // k + 1 entries (coefficients and |w|^2)
     double *d_norm = d_coeff + k + 2;
     p += align_up((size_t)(4 * k + 8) * sizeof(double));
-    double *partial = (double *)p;
-    p += align_up((size_t)kRedWaves * (k + 2) * sizeof(double));
+    double *partial = (double *)p;                        // inner products, k + 2 per block
+    double *npart = partial + (size_t)kRedBlocks * (k + 2);  // |w|^2, one per block
+    p += align_up((size_t)kRedBlocks * (k + 3) * sizeof(double));
     double *rows = (double *)p;  // three rows of orthogonality estimates, k + 2 entries each
     double *d_anorm = rows + 3 * (k + 2);
     p += align_up((size_t)(3 * (k + 2) + 1) * sizeof(double));
@@ -596,42 +680,45 @@ int sparc_lanczos(const sparc_op *op, int32_t k, const double *v0, double *alpha
     double *w = V + (long long)k * n;
     const double eps1 = 0.5 * std::sqrt((double)n) * 2.220446049250313e-16;
 
-    const dim3 sg = stream_grid(n);
     const dim3 rg(kRedBlocks), tb(256);
     const int *always = nullptr;
     int st;
     hipLaunchKernelGGL(omega_init, dim3(1), tb, 0, s, rows, k + 2, d_state, d_anorm);
     // V_0 = v0 / |v0|
-    hipLaunchKernelGGL(multidot_kernel, rg, tb, 0, s, v0, (long long)n, 0, v0, n, partial, always);
-    hipLaunchKernelGGL(finish_sums, dim3(1), tb, 0, s, partial, 1, d_norm, nullptr, -1, 1, always);
-    hipLaunchKernelGGL(scale_by_inverse, sg, tb, 0, s, V, v0, d_norm, n);
+    hipLaunchKernelGGL(multidot_kernel, rg, tb, 0, s, v0, (long long)n, 0, v0, n, npart, always);
+    hipLaunchKernelGGL(scale_by_norm, rg, tb, 0, s, V, v0, d_norm, (const double *)npart, always, n);
     StepLaunch L = choose_step_launch(op, SPARC_F64, 1);
     StepCoef hc{1.0, 0.0, 0.0, 0};
     for (int j = 0; j < k; ++j) {
         double *vj = V + (long long)j * n;
         if ((st = launch_h_step(op, SPARC_F64, vj, n, nullptr, 0, w, n, 1, G, hc, L, s))) return st;
-        // alpha_j = v_j^T w
+        // block partials of alpha_j = v_j^T w
         hipLaunchKernelGGL(multidot_kernel, rg, tb, 0, s, vj, (long long)n, 1, w, n, partial, always);
-        hipLaunchKernelGGL(finish_sums, dim3(1), tb, 0, s, partial, 2, d_coeff, d_alpha + j, 0, 0, always);
-        if (j + 1 == k) break;
-        // w -= alpha_j v_j + beta_{j-1} v_{j-1};  beta_j = |w|
+        if (j + 1 == k) {
+            hipLaunchKernelGGL(finish_sums, dim3(1), tb, 0, s, (const double *)partial, 2, d_coeff, d_alpha + j, 0,
+                               0, always);
+            break;
+        }
+        // alpha_j; w -= alpha_j v_j + beta_{j-1} v_{j-1}; partials of |w|^2
         hipLaunchKernelGGL(lanczos_3term, rg, tb, 0, s, w, (const double *)vj, (const double *)(vj - (j > 0 ? n : 0)),
-                           (const double *)(d_alpha + j), (const double *)(j > 0 ? d_beta + j - 1 : nullptr), n,
-                           partial);
+                           (const double *)partial, d_alpha + j,
+                           (const double *)(j > 0 ? d_beta + j - 1 : nullptr), n, npart);
         // beta_j and the orthogonality estimates; when needed, one classical
-        // Gram-Schmidt pass against v_0 .. v_j and a new beta_j
+        // Gram-Schmidt pass against v_0 .. v_j, whose new |w|^2 partials the
+        // scaling kernel finishes into beta_j
         const double *Wc = rows + (size_t)(j % 3) * (k + 2);
         const double *Wp = rows + (size_t)((j + 2) % 3) * (k + 2);
         double *Wn = rows + (size_t)((j + 1) % 3) * (k + 2);
         hipLaunchKernelGGL(omega_kernel, dim3(1), tb, 0, s, (const double *)d_alpha, d_beta, j, eps1, Wp, Wc, Wn,
-                           d_state, d_anorm, (const double *)partial);
+                           d_state, d_anorm, (const double *)npart);
         const int nv = j + 1;
         const int *full = d_state;
         hipLaunchKernelGGL(multidot_kernel, rg, tb, 0, s, V, (long long)n, nv, w, n, partial, full);
-        hipLaunchKernelGGL(finish_sums, dim3(nv), tb, 0, s, partial, nv + 1, d_coeff, nullptr, -1, 0, full);
-        hipLaunchKernelGGL(orth_apply_norm, rg, tb, 0, s, w, V, (long long)n, nv, d_coeff, n, partial, full);
-        hipLaunchKernelGGL(finish_sums, dim3(1), tb, 0, s, partial, 1, d_beta + j, nullptr, -1, 1, full);
-        hipLaunchKernelGGL(scale_by_inverse, sg, tb, 0, s, vj + n, w, d_beta + j, n);
+        hipLaunchKernelGGL(finish_sums, dim3(nv), tb, 0, s, (const double *)partial, nv + 1, d_coeff, nullptr, -1, 0,
+                           full);
+        hipLaunchKernelGGL(orth_apply_norm, rg, tb, 0, s, w, V, (long long)n, nv, d_coeff, n, npart, full);
+        hipLaunchKernelGGL(scale_by_norm, rg, tb, 0, s, vj + n, (const double *)w, d_beta + j, (const double *)npart,
+                           full, n);
         SPARC_HIP(hipGetLastError());
     }
     SPARC_HIP(hipGetLastError());

@@ -136,6 +136,20 @@ __device__ __forceinline__ void scatter_item(const ScatterArgs<T> &s, int b, int
     const int a0 = s.blk_at[b];
     const int na = s.blk_at[b + 1] - a0;
     const long long split = (long long)s.nproj_total * s.ns;
+    // this thread's node: its output values and first entry are requested
+    // before the table is built, so their latency overlaps it
+    const int pi = s.blk_pt[b] + threadIdx.x;
+    const bool own = pi < s.blk_pt[b + 1];
+    int gpt = 0, e0 = 0, e1 = 0;
+    T cur[kScatterCols] = {};
+    if (own) {
+        gpt = s.pts[pi];
+        e0 = s.ent_off[pi];
+        e1 = s.ent_off[pi + 1];
+#pragma unroll
+        for (int cc = 0; cc < kScatterCols; ++cc)
+            if (c0 + cc < s.ns) cur[cc] = s.out[(long long)(c0 + cc) * s.ldo + gpt];
+    }
     for (int idx = threadIdx.x; idx < na * kMaxProj * kScatterCols; idx += 256) {
         const int slot = idx / (kMaxProj * kScatterCols);
         const int p = (idx / kScatterCols) % kMaxProj;
@@ -152,11 +166,9 @@ __device__ __forceinline__ void scatter_item(const ScatterArgs<T> &s, int b, int
         gl[slot][p][cc] = v;
     }
     __syncthreads();
-    const int pi = s.blk_pt[b] + threadIdx.x;
-    if (pi >= s.blk_pt[b + 1]) return;
+    if (!own) return;
     T acc[kScatterCols] = {};
-    const int e1 = s.ent_off[pi + 1];
-    for (int e = s.ent_off[pi]; e < e1; ++e) {
+    for (int e = e0; e < e1; ++e) {
         const int4 en = s.ent[e];
         for (int p = 0; p < en.w; ++p) {
             const T cv = s.chi[en.x + (long long)p * en.y];
@@ -164,13 +176,9 @@ __device__ __forceinline__ void scatter_item(const ScatterArgs<T> &s, int b, int
             for (int cc = 0; cc < kScatterCols; ++cc) acc[cc] += cv * gl[en.z][p][cc];
         }
     }
-    const int gpt = s.pts[pi];
 #pragma unroll
     for (int cc = 0; cc < kScatterCols; ++cc)
-        if (c0 + cc < s.ns) {
-            T *o = s.out + (long long)(c0 + cc) * s.ldo + gpt;
-            *o += s.alpha * acc[cc];
-        }
+        if (c0 + cc < s.ns) s.out[(long long)(c0 + cc) * s.ldo + gpt] = cur[cc] + s.alpha * acc[cc];
 }
 
 }  // namespace sparc
