@@ -166,17 +166,43 @@ __global__ void __launch_bounds__(256) orth_apply_norm(double *w, const double *
     if (threadIdx.x == 0) partial[blockIdx.x] = t;
 }
 
-// three-term Lanczos step.  alpha_j = v_j^T w is first finished from the block
-// partials of the inner-product pass (entry 0 of stride 2; block 0 stores it),
+// alpha_j = v_j^T H v_j from its two parts: the step kernel's workgroup
+// partials of v^T (H_loc v), and the projections g_p = chi_p^T v (the
+// gather's split partials, nproj of them per split), since
+// v^T V_nl v = sum_p hg_p g_p^2.  One fixed order in every block.
+__device__ inline double lanczos_alpha(const double *dot, int nb, const double *gpart, const double *hg, int nproj,
+                                       double *red)
+{
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) v += dot[b];
+    for (int p = threadIdx.x; p < nproj; p += 256) {
+        double g = 0.0;
+#pragma unroll
+        for (int q = 0; q < kGatherSplit; ++q) g += gpart[(long long)q * nproj + p];
+        v += hg[p] * g * g;
+    }
+    return block_sum(v, red);
+}
+
+__global__ void __launch_bounds__(256) alpha_finish(const double *dot, int nb, const double *gpart, const double *hg,
+                                                    int nproj, double *alpha)
+{
+    __shared__ double red[4];
+    const double a = lanczos_alpha(dot, nb, gpart, hg, nproj, red);
+    if (threadIdx.x == 0) *alpha = a;
+}
+
+// three-term Lanczos step: alpha_j is finished first (block 0 stores it),
 // then w -= alpha_j v_j + beta_{j-1} v_{j-1} (bprev may be null at j = 0) and
 // partial[b] = sum over block b's points of the new w^2
 __global__ void __launch_bounds__(256) lanczos_3term(double *w, const double *__restrict__ vj,
-                                                     const double *__restrict__ vjm, const double *apart,
+                                                     const double *__restrict__ vjm, const double *dot, int nb,
+                                                     const double *gpart, const double *hg, int nproj,
                                                      double *alpha, const double *bprev, long long n,
                                                      double *__restrict__ partial)
 {
     __shared__ double red[4];
-    const double a = sum_partials(apart, 2, 0, red);
+    const double a = lanczos_alpha(dot, nb, gpart, hg, nproj, red);
     if (blockIdx.x == 0 && threadIdx.x == 0) *alpha = a;
     const double b = bprev ? *bprev : 0.0;
     const double *vm = bprev ? vjm : vj;
@@ -640,12 +666,13 @@ size_t sparc_lanczos_workspace_bytes(const sparc_op *op, int32_t k)
     b += gather_bytes(op, SPARC_F64, 1);                                  // gathered projections
     b += align_up((size_t)(4 * k + 8) * sizeof(double));                  // alpha, beta, coeff, norm
     b += align_up((size_t)kRedBlocks * (k + 3) * sizeof(double));         // block partial sums
+    b += align_up((size_t)step_dot_blocks(op) * sizeof(double));           // v^T H_loc v partials
     b += align_up((size_t)(3 * (k + 2) + 1) * sizeof(double));            // omega rows, ||T|| estimate
     b += align_up(2 * sizeof(int));                                         // reorthogonalisation state
     return b;
 }
 
-// Lanczos with partial re-orthogonalisation: w = H v_j, alpha_j = v_j^T w,
+// Lanczos with partial re-orthogonalisation: w = H v_j, alpha_j = v_j^T H v_j,
 // w -= alpha_j v_j + beta_{j-1} v_{j-1}, beta_j = |w|; when the omega
 // recurrence (omega_kernel) estimates a loss of orthogonality beyond sqrt(eps),
 // one classical Gram-Schmidt pass against v_0 .. v_j (c = V^T w, w -= V c) and
@@ -673,6 +700,9 @@ int sparc_lanczos(const sparc_op *op, int32_t k, const double *v0, double *alpha
     double *partial = (double *)p;                        // inner products, k + 2 per block
     double *npart = partial + (size_t)kRedBlocks * (k + 2);  // |w|^2, one per block
     p += align_up((size_t)kRedBlocks * (k + 3) * sizeof(double));
+    double *dotp = (double *)p;  // step kernel partials of v_j^T H_loc v_j
+    const int ndot = (int)step_dot_blocks(op);
+    p += align_up((size_t)ndot * sizeof(double));
     double *rows = (double *)p;  // three rows of orthogonality estimates, k + 2 entries each
     double *d_anorm = rows + 3 * (k + 2);
     p += align_up((size_t)(3 * (k + 2) + 1) * sizeof(double));
@@ -687,22 +717,22 @@ int sparc_lanczos(const sparc_op *op, int32_t k, const double *v0, double *alpha
     // V_0 = v0 / |v0|
     hipLaunchKernelGGL(multidot_kernel, rg, tb, 0, s, v0, (long long)n, 0, v0, n, npart, always);
     hipLaunchKernelGGL(scale_by_norm, rg, tb, 0, s, V, v0, d_norm, (const double *)npart, always, n);
-    StepLaunch L = choose_step_launch(op, SPARC_F64, 1);
-    StepCoef hc{1.0, 0.0, 0.0, 0};
+    const int nproj = op->nproj_total;
     for (int j = 0; j < k; ++j) {
         double *vj = V + (long long)j * n;
-        if ((st = launch_h_step(op, SPARC_F64, vj, n, nullptr, 0, w, n, 1, G, hc, L, s))) return st;
-        // block partials of alpha_j = v_j^T w
-        hipLaunchKernelGGL(multidot_kernel, rg, tb, 0, s, vj, (long long)n, 1, w, n, partial, always);
+        // w = H v_j, with the two parts of alpha_j = v_j^T H v_j left as partials
+        if ((st = launch_gather(op, SPARC_F64, vj, n, 1, G, s))) return st;
+        if ((st = launch_step_dot_f64(op, vj, w, dotp, s))) return st;
+        if ((st = launch_scatter(op, SPARC_F64, w, n, 1, G, 1.0, s))) return st;
         if (j + 1 == k) {
-            hipLaunchKernelGGL(finish_sums, dim3(1), tb, 0, s, (const double *)partial, 2, d_coeff, d_alpha + j, 0,
-                               0, always);
+            hipLaunchKernelGGL(alpha_finish, dim3(1), tb, 0, s, (const double *)dotp, ndot, (const double *)G,
+                               (const double *)op->d_hg64, nproj, d_alpha + j);
             break;
         }
         // alpha_j; w -= alpha_j v_j + beta_{j-1} v_{j-1}; partials of |w|^2
         hipLaunchKernelGGL(lanczos_3term, rg, tb, 0, s, w, (const double *)vj, (const double *)(vj - (j > 0 ? n : 0)),
-                           (const double *)partial, d_alpha + j,
-                           (const double *)(j > 0 ? d_beta + j - 1 : nullptr), n, npart);
+                           (const double *)dotp, ndot, (const double *)G, (const double *)op->d_hg64, nproj,
+                           d_alpha + j, (const double *)(j > 0 ? d_beta + j - 1 : nullptr), n, npart);
         // beta_j and the orthogonality estimates; when needed, one classical
         // Gram-Schmidt pass against v_0 .. v_j, whose new |w|^2 partials the
         // scaling kernel finishes into beta_j

@@ -43,13 +43,26 @@ namespace sparc {
 const TileShape kShapes[kNumShapes] = {{32, 2, 256}, {32, 2, 512}, {32, 2, 768}, {64, 2, 256},
                                        {64, 2, 512}, {32, 4, 256}};
 
-template <typename T, int TZ, int RY, int NT, bool PREV, bool STREAM, typename TI>
+template <typename T, int TZ, int RY, int NT, bool PREV, bool STREAM, typename TI, bool DOT = false>
 __global__ void __launch_bounds__(NT) step_kernel(const StepArgs<T, TI> a)
 {
-    using K = StepKernel<T, TZ, RY, NT, PREV, STREAM, TI>;
+    using K = StepKernel<T, TZ, RY, NT, PREV, STREAM, TI, DOT>;
     __shared__ T lds[2][K::SY * K::SZ];
     K k(a);
     k.run(blockIdx.x, lds);
+    if constexpr (DOT) {
+        // fixed-order workgroup sum of the per-thread products
+        __shared__ T red[NT / 64];
+        T v = k.dacc;
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            T t = red[0];
+            for (int i = 1; i < NT / 64; ++i) t += red[i];
+            a.dot[blockIdx.x] = t;
+        }
+    }
 }
 
 StepLaunch choose_step_launch(const sparc_op *op, int dtype, int ns)
@@ -117,6 +130,7 @@ static int launch_step_t(const sparc_op *op, const void *yk, int64_t ldk, const 
     if (nb > 0x7fffffffLL) return fail(SPARC_E_SHAPE, "too many workgroups for one launch");
     a.nblocks = (int)nb;
     a.remap = 1;
+    a.dot = nullptr;
     a.c0 = (T)(-3.0 * op->w[0]);
     for (int p = 1; p <= kMaxRadius; ++p) a.cp[p - 1] = (T)(-0.5 * op->w[p]);
     a.alpha = (T)c.alpha;
@@ -149,6 +163,64 @@ int launch_step(const sparc_op *op, int dtype, const void *yk, int64_t ldk, cons
     if (dtype == SPARC_F64)
         return launch_step_t<double>(op, yk, ldk, yprev, ldp, out, ldo, ns, c, L, stream, op->d_veff64);
     return launch_step_t<float>(op, yk, ldk, yprev, ldp, out, ldo, ns, c, L, stream, op->d_veff32);
+}
+
+// The single-vector FP64 step of the Lanczos iteration: 32 x 16 patches and
+// the default x split, independent of any launch override, so that the
+// workgroup count (one partial each) is fixed by the grid alone.
+static StepLaunch dot_launch(const sparc_op *op)
+{
+    const TileShape &s = kShapes[0];
+    const long long tiles = (long long)((op->n[1] + s.ty() - 1) / s.ty()) * ((op->n[2] + s.tz - 1) / s.tz);
+    const long long waves = tiles * (s.nt / 64);
+    long long nchunks = (8192 + waves - 1) / waves;
+    nchunks = std::max<long long>(1, std::min<long long>(nchunks, op->n[0] / 4));
+    StepLaunch L;
+    L.shape = 0;
+    L.chunk_x = (int)((op->n[0] + nchunks - 1) / nchunks);
+    return L;
+}
+
+long long step_dot_blocks(const sparc_op *op)
+{
+    const TileShape &s = kShapes[0];
+    const StepLaunch L = dot_launch(op);
+    return (long long)((op->n[0] + L.chunk_x - 1) / L.chunk_x) * ((op->n[1] + s.ty() - 1) / s.ty()) *
+           ((op->n[2] + s.tz - 1) / s.tz);
+}
+
+int launch_step_dot_f64(const sparc_op *op, const double *v, double *out, double *dot, hipStream_t stream)
+{
+    const TileShape &s = kShapes[0];
+    const StepLaunch L = dot_launch(op);
+    StepArgs<double, double> a;
+    a.yk = v;
+    a.yprev = nullptr;
+    a.out = out;
+    a.veff = op->d_veff64;
+    a.ldk = a.ldp = a.ldo = op->nd;
+    a.n1 = op->n[0];
+    a.n2 = op->n[1];
+    a.n3 = op->n[2];
+    a.tiles_y = (op->n[1] + s.ty() - 1) / s.ty();
+    a.tiles_z = (op->n[2] + s.tz - 1) / s.tz;
+    a.chunk_x = L.chunk_x;
+    a.nchunks = (op->n[0] + L.chunk_x - 1) / L.chunk_x;
+    const long long nb = step_dot_blocks(op);
+    if (nb > 0x7fffffffLL) return fail(SPARC_E_SHAPE, "too many workgroups for one launch");
+    a.nblocks = (int)nb;
+    a.remap = 1;
+    a.dot = dot;
+    a.c0 = -3.0 * op->w[0];
+    for (int p = 1; p <= kMaxRadius; ++p) a.cp[p - 1] = -0.5 * op->w[p];
+    a.alpha = 1.0;
+    a.beta = 0.0;
+    a.shift = 0.0;
+    ProfScope prof(3, stream);
+    hipLaunchKernelGGL((step_kernel<double, 32, 2, 256, false, false, double, true>), dim3(a.nblocks), dim3(256), 0,
+                       stream, a);
+    SPARC_HIP(hipGetLastError());
+    return SPARC_OK;
 }
 
 }  // namespace sparc

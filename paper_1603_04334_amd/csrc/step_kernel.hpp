@@ -19,13 +19,15 @@ struct StepArgs {
     int tiles_y, tiles_z, nchunks, chunk_x;
     int nblocks;
     int remap;         // 1: spread consecutive block indices over the XCDs' patch ranges
+    T *dot;            // DOT launches: per-workgroup sum of yk (H_loc yk) over its points
     T c0;              // centre coefficient of -1/2 lap_h: -3 w_0
     T cp[kMaxRadius];  // -1/2 w_p, p = 1..kMaxRadius (zero beyond the op's radius)
     T alpha, beta, shift;
 };
 
 // STREAM: Y_{k-1} and the output bypass the caches (non-temporal accesses)
-template <typename T, int TZ, int RY, int NT, bool PREV, bool STREAM = false, typename TI = T>
+// DOT: each thread also accumulates yk(x) * out(x) over its points (dacc)
+template <typename T, int TZ, int RY, int NT, bool PREV, bool STREAM = false, typename TI = T, bool DOT = false>
 struct StepKernel {
     static constexpr int R = kMaxRadius;
     static constexpr int QL = 2 * R + 1;     // queue length: planes x-R .. x+R
@@ -57,6 +59,7 @@ struct StepKernel {
     bool hok[NH];
     int hl[NH];
     T q[RY][QL];
+    T dacc = T(0);
 
     __device__ StepKernel(const StepArgs<T, TI> &args) : a(args) {}
 
@@ -139,6 +142,7 @@ struct StepKernel {
             T res = a.alpha * acc;
             if constexpr (PREV) res -= a.beta * pcur[r];
             if (pok[r]) {
+                if constexpr (DOT) dacc += c * res;
                 if constexpr (STREAM)
                     __builtin_nontemporal_store(res, &po[pbase + pofs[r]]);  // written once
                 else
