@@ -25,6 +25,44 @@ struct StepArgs {
     T alpha, beta, shift;
 };
 
+// Global accesses are raw buffer loads and stores through one descriptor per
+// plane: the plane's base address and byte size (zero for a plane outside
+// the grid), with 32-bit in-plane byte offsets kept in registers.  A point
+// outside the grid carries the offset kOutside, which the descriptor's range
+// check turns into a load of zero or a dropped store, so neither the bounds
+// selects nor 64-bit address arithmetic are spent per access.
+constexpr unsigned kOutside = 0x80000000u;
+constexpr int kBufWord3 = 0x00020000;  // raw (untyped) buffer, 32-bit data format
+constexpr int kNonTemporal = 2;        // cache-policy bit: non-temporal
+
+template <typename E>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const E *col, int t, int n1, long long P)
+{
+    const bool in = t >= 0 && t < n1;
+    const E *base = col + (in ? (long long)t * P : 0LL);
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, 0, in ? (int)(P * (long long)sizeof(E)) : 0, kBufWord3);
+}
+
+template <typename E, int AUX>
+__device__ __forceinline__ E buf_load(__amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    if constexpr (sizeof(E) == 4)
+        return __builtin_bit_cast(E, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX));
+    else
+        return __builtin_bit_cast(E, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX));
+}
+
+template <typename E, int AUX>
+__device__ __forceinline__ void buf_store(E v, __amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    if constexpr (sizeof(E) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, AUX);
+    } else {
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, off, 0, AUX);
+    }
+}
+
 // STREAM: Y_{k-1} and the output bypass the caches (non-temporal accesses)
 // DOT: each thread also accumulates yk(x) * out(x) over its points (dacc)
 template <typename T, int TZ, int RY, int NT, bool PREV, bool STREAM = false, typename TI = T, bool DOT = false>
@@ -53,10 +91,10 @@ struct StepKernel {
     T *out;
     long long P;
     int lz, lyg, xs, xe;
-    int pofs[RY];    // in-plane offset of the own points
+    unsigned pofs_i[RY];  // in-plane byte offsets of the own points in yk (TI), or kOutside
+    unsigned pofs_t[RY];  // the same in the T arrays (V_eff, yprev, out)
     bool pok[RY];
-    int hofs[NH];    // in-plane offset of the halo values (0 when outside)
-    bool hok[NH];
+    unsigned hofs[NH];    // in-plane byte offsets of the halo values in yk, or kOutside
     int hl[NH];
     T q[RY][QL];
     T dacc = T(0);
@@ -65,33 +103,20 @@ struct StepKernel {
 
     __device__ __forceinline__ void load_stage(Stage &s, int t) const
     {
-        const bool tin = t < a.n1;
-        const long long base = (long long)(tin ? t : 0) * P;
+        const auto rk = plane_rsrc(yk, t, a.n1, P);
 #pragma unroll
-        for (int i = 0; i < NH; ++i) {
-            const bool ok = tin && hok[i];
-            const T v = (T)yk[base + (ok ? hofs[i] : 0)];
-            s.h[i] = ok ? v : T(0);
-        }
-        const int th = t + R;
-        const bool hin = th < a.n1;
-        const long long hbase = (long long)(hin ? th : 0) * P;
+        for (int i = 0; i < NH; ++i) s.h[i] = (T)buf_load<TI, 0>(rk, hofs[i]);
+        const auto rh = plane_rsrc(yk, t + R, a.n1, P);
 #pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            const bool ok = hin && pok[r];
-            const T v = (T)yk[hbase + (ok ? pofs[r] : 0)];
-            s.qh[r] = ok ? v : T(0);
-        }
+        for (int r = 0; r < RY; ++r) s.qh[r] = (T)buf_load<TI, 0>(rh, pofs_i[r]);
+        const auto rv = plane_rsrc(a.veff, t, a.n1, P);
 #pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            const long long g = base + (pok[r] ? pofs[r] : 0);
-            s.v[r] = a.veff[g];
-            if constexpr (PREV) {
-                if constexpr (STREAM)
-                    s.p[r] = __builtin_nontemporal_load(&yp[g]);  // read once: keep it out of the caches
-                else
-                    s.p[r] = yp[g];
-            }
+        for (int r = 0; r < RY; ++r) s.v[r] = buf_load<T, 0>(rv, pofs_t[r]);
+        if constexpr (PREV) {
+            // read once: streamed past the caches when the block is large
+            const auto rp = plane_rsrc(yp, t, a.n1, P);
+#pragma unroll
+            for (int r = 0; r < RY; ++r) s.p[r] = buf_load<T, STREAM ? kNonTemporal : 0>(rp, pofs_t[r]);
         }
     }
 
@@ -124,8 +149,7 @@ struct StepKernel {
         // request plane x+2 into the stage just consumed
         load_stage(s, x + 2);
 
-        T *po = out;
-        const long long pbase = (long long)x * P;
+        const auto ro = plane_rsrc((const T *)out, x, a.n1, P);
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             const int li = (R + lyg * RY + r) * SZ + R + lz;
@@ -141,13 +165,10 @@ struct StepKernel {
             acc += (vcur[r] - a.shift) * c;
             T res = a.alpha * acc;
             if constexpr (PREV) res -= a.beta * pcur[r];
-            if (pok[r]) {
-                if constexpr (DOT) dacc += c * res;
-                if constexpr (STREAM)
-                    __builtin_nontemporal_store(res, &po[pbase + pofs[r]]);  // written once
-                else
-                    po[pbase + pofs[r]] = res;
-            }
+            if constexpr (DOT)
+                if (pok[r]) dacc += c * res;
+            // written once; points outside the grid are dropped by the range check
+            buf_store<T, STREAM ? kNonTemporal : 0>(res, ro, pofs_t[r]);
         }
     }
 
@@ -194,7 +215,9 @@ struct StepKernel {
         for (int r = 0; r < RY; ++r) {
             const int y = y0 + lyg * RY + r;
             pok[r] = (z < n3) && (y < n2);
-            pofs[r] = y * n3 + z;
+            const unsigned e = (unsigned)(y * n3 + z);
+            pofs_i[r] = pok[r] ? e * (unsigned)sizeof(TI) : kOutside;
+            pofs_t[r] = pok[r] ? e * (unsigned)sizeof(T) : kOutside;
         }
 #pragma unroll
         for (int i = 0; i < NH; ++i) {
@@ -212,8 +235,8 @@ struct StepKernel {
             }
             hl[i] = (ly >= 0) ? ly * SZ + lzz : -1;
             const int gy = y0 - R + ly, gz = z0 - R + lzz;
-            hok[i] = ly >= 0 && gy >= 0 && gy < n2 && gz >= 0 && gz < n3;
-            hofs[i] = hok[i] ? gy * n3 + gz : 0;
+            const bool hok = ly >= 0 && gy >= 0 && gy < n2 && gz >= 0 && gz < n3;
+            hofs[i] = hok ? (unsigned)(gy * n3 + gz) * (unsigned)sizeof(TI) : kOutside;
         }
         xs = chunk * a.chunk_x;
         xe = min(a.n1, xs + a.chunk_x);
@@ -221,14 +244,9 @@ struct StepKernel {
         // queue: planes xs-R .. xs+R-1 (heads are filled from the stages)
 #pragma unroll
         for (int d = 0; d < 2 * R; ++d) {
-            const int xx = xs - R + d;
-            const bool in = xx >= 0 && xx < a.n1;
+            const auto rq = plane_rsrc(yk, xs - R + d, a.n1, P);
 #pragma unroll
-            for (int r = 0; r < RY; ++r) {
-                const bool ok = in && pok[r];
-                const T v = (T)yk[(long long)(ok ? xx : 0) * P + (ok ? pofs[r] : 0)];
-                q[r][d] = ok ? v : T(0);
-            }
+            for (int r = 0; r < RY; ++r) q[r][d] = (T)buf_load<TI, 0>(rq, pofs_i[r]);
         }
         Stage st[2];
         load_stage(st[0], xs);
