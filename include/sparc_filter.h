@@ -95,7 +95,8 @@ typedef struct sparc_op sparc_op;
  * projector cubes, and nothing else; it may be used from several streams at
  * once (sparc_op_set_launch aside).  Synchronous.
  * Errors: SPARC_E_ARG (null pointers, natoms < 0, nproj outside 1..16),
- * SPARC_E_SHAPE (n < 1, h <= 0, radius outside 1..6, cube outside the grid),
+ * SPARC_E_SHAPE (n < 1, n[1]*n[2] >= 2^28, h <= 0, radius outside 1..6,
+ * cube outside the grid),
  * SPARC_E_NOMEM, SPARC_E_HIP. */
 int sparc_op_create(const sparc_grid *grid, const double *veff, int32_t natoms,
                     const sparc_atom *atoms, sparc_op **out);

@@ -188,8 +188,10 @@ int sparc_op_create(const sparc_grid *grid, const double *veff, int32_t natoms, 
         if (grid->n[d] < 1) return fail(SPARC_E_SHAPE, "grid extents must be >= 1");
     if (!(grid->h > 0)) return fail(SPARC_E_SHAPE, "grid spacing must be > 0");
     if (grid->radius < 1 || grid->radius > kMaxRadius) return fail(SPARC_E_SHAPE, "radius must be in 1..6");
+    // one FP64 plane must stay below 2 GiB (32-bit in-plane byte offsets in the kernels)
     const int64_t plane = (int64_t)grid->n[1] * grid->n[2];
-    if (plane > 0x7fffffffLL) return fail(SPARC_E_SHAPE, "n[1]*n[2] must fit in 32 bits");
+    if (plane >= (1LL << 28)) return fail(SPARC_E_SHAPE, "n[1]*n[2] must be below 2^28");
+    const int64_t nd_all = (int64_t)grid->n[0] * plane;
 
     sparc_op *op = new (std::nothrow) sparc_op();
     if (!op) return fail(SPARC_E_NOMEM, "host allocation failed");
@@ -201,7 +203,7 @@ int sparc_op_create(const sparc_grid *grid, const double *veff, int32_t natoms, 
     for (int d = 0; d < 3; ++d) op->n[d] = grid->n[d];
     op->h = grid->h;
     op->radius = grid->radius;
-    op->nd = (int64_t)grid->n[0] * plane;
+    op->nd = nd_all;
     laplacian_weights(op->radius, op->h, op->w);
 
     const int64_t nd = op->nd;

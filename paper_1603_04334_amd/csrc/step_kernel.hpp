@@ -30,7 +30,9 @@ struct StepArgs {
 // the grid), with 32-bit in-plane byte offsets kept in registers.  A point
 // outside the grid carries the offset kOutside, which the descriptor's range
 // check turns into a load of zero or a dropped store, so neither the bounds
-// selects nor 64-bit address arithmetic are spent per access.
+// selects nor 64-bit address arithmetic are spent per access.  A plane
+// stays below 2 GiB (checked when the op is built), so kOutside is always
+// out of range.
 constexpr unsigned kOutside = 0x80000000u;
 constexpr int kBufWord3 = 0x00020000;  // raw (untyped) buffer, 32-bit data format
 constexpr int kNonTemporal = 2;        // cache-policy bit: non-temporal

@@ -47,3 +47,17 @@ def test_null_arguments_rejected_without_device():
     assert lib.sparc_h_apply(None, 0, None, 0, None, 0, 1, None, 0, None) == binding.SPARC_E_ARG
     assert lib.sparc_cheb_filter(None, 0, None, 0, None, 0, 1, 20, 0.0, 1.0, 2.0, None, 0, None) == binding.SPARC_E_ARG
     assert lib.sparc_op_destroy(None) == 0
+
+
+def test_invalid_grids_rejected_without_device():
+    """Shape checks run before any device work: a plane of 2^28 nodes or more
+    (32-bit in-plane byte offsets in FP64) and degenerate grids are refused."""
+    lib = _lib_or_skip()
+    h = ctypes.c_void_p()
+    veff = (ctypes.c_double * 1)(0.0)
+    for n, hh, r in (((1, 1 << 14, 1 << 14), 0.5, 6), ((0, 4, 4), 0.5, 6), ((4, 4, 4), 0.0, 6), ((4, 4, 4), 0.5, 7)):
+        g = binding.sparc_grid()
+        g.n[0], g.n[1], g.n[2] = n
+        g.h, g.radius = hh, r
+        assert lib.sparc_op_create(ctypes.byref(g), veff, 0, None, ctypes.byref(h)) == binding.SPARC_E_SHAPE
+        assert not h.value
