@@ -405,7 +405,7 @@ def main():
         "filter_only": {"value": updates / t_filter, "ms": t_filter * 1e3},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "step_kernel<T,32,2,256,prev> (fused stencil + local potential + recurrence)",
+                     "kernel": "step_kernel (fused stencil + local potential + recurrence, with Y_{k-1})",
                      "launches": n_launch, "avg_launch_us": avg_s * 1e6,
                      "alg_bytes_per_launch": alg},
         "gather_kernel": {"launches": n_g, "avg_launch_us": ms_g / max(n_g, 1) * 1e3},
