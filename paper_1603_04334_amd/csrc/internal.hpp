@@ -112,6 +112,8 @@ struct StepLaunch {
 };
 
 StepLaunch choose_step_launch(const sparc_op *op, int dtype, int ns);
+// launch of the FP64 step on an FP32 block (launch_step_f32_to_f64)
+StepLaunch choose_mixed_launch(const sparc_op *op, int ns);
 
 // bytes of the gather's partial projections for ns columns
 inline size_t gather_bytes(const sparc_op *op, int dtype, int ns)

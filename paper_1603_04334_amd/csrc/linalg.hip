@@ -831,7 +831,7 @@ int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_
         // H in FP64 on the FP32 values, widened as they are loaded
         const float *Yf = (const float *)Y;
         if ((st = launch_gather_f32_to_f64(op, Yf, ldy, ns, G, s))) return st;
-        if ((st = launch_step_f32_to_f64(op, Yf, ldy, HY, nd, ns, hc, L, s))) return st;
+        if ((st = launch_step_f32_to_f64(op, Yf, ldy, HY, nd, ns, hc, choose_mixed_launch(op, ns), s))) return st;
         if ((st = launch_scatter(op, SPARC_F64, HY, nd, ns, G, 1.0, s))) return st;
         hipLaunchKernelGGL(rr_project_kernel<float>, pg, dim3(256), 0, s, Yf, (long long)ldy, (const double *)HY, nd,
                            nd, ns, kc, partial);

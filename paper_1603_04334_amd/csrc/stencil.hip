@@ -65,27 +65,49 @@ __global__ void __launch_bounds__(NT) step_kernel(const StepArgs<T, TI> a)
     }
 }
 
+// split x so that about 8192 waves are in flight, keeping >= 4 planes per chunk
+static int default_chunk(const sparc_op *op, int shape, int ns)
+{
+    const TileShape &s = kShapes[shape];
+    const long long tiles = (long long)((op->n[1] + s.ty() - 1) / s.ty()) * ((op->n[2] + s.tz - 1) / s.tz);
+    const long long waves = tiles * ns * (s.nt / 64);
+    long long nchunks = (8192 + waves - 1) / waves;
+    nchunks = std::max<long long>(1, std::min<long long>(nchunks, op->n[0] / 4));
+    return (int)((op->n[0] + nchunks - 1) / nchunks);
+}
+
+// taller patches cut the halo re-reads but pad n[1] up to a multiple of their
+// height: take the taller one (shape) when its measured per-point time
+// (speed, relative to 32 x 16) outweighs the padding
+static int pick_taller(const sparc_op *op, int shape, double speed)
+{
+    const int ty = kShapes[shape].ty();
+    const long long pad16 = (op->n[1] + 15) / 16 * 16, padt = (op->n[1] + ty - 1) / ty * ty;
+    return speed * padt < pad16 ? shape : 0;
+}
+
 StepLaunch choose_step_launch(const sparc_op *op, int dtype, int ns)
 {
     StepLaunch L;
     // 32 x 16 patches of 256 threads measured fastest in FP64 on the 96^3 and
     // larger grids; in FP32, 32 x 48 patches of 768 threads run about 4.5%
-    // faster per point, which pays unless padding n[1] to 48 rows costs more
-    L.shape = 0;
-    if (dtype == SPARC_F32) {
-        const long long pad16 = (op->n[1] + 15) / 16 * 16, pad48 = (op->n[1] + 47) / 48 * 48;
-        if (0.955 * pad48 < pad16) L.shape = 2;
-    }
+    // faster per point
+    L.shape = dtype == SPARC_F32 ? pick_taller(op, 2, 0.955) : 0;
     const bool tuned = tune_applies(op, dtype, ns);
     if (tuned && op->tune_shape[dtype] >= 0) L.shape = op->tune_shape[dtype];
-    const TileShape &s = kShapes[L.shape];
-    const long long tiles = (long long)((op->n[1] + s.ty() - 1) / s.ty()) * ((op->n[2] + s.tz - 1) / s.tz);
-    const long long waves = tiles * ns * (s.nt / 64);
-    // split x so that about 8192 waves are in flight, keeping >= 4 planes per chunk
-    long long nchunks = (8192 + waves - 1) / waves;
-    nchunks = std::max<long long>(1, std::min<long long>(nchunks, op->n[0] / 4));
-    L.chunk_x = (int)((op->n[0] + nchunks - 1) / nchunks);
+    L.chunk_x = default_chunk(op, L.shape, ns);
     if (tuned && op->tune_chunk[dtype] > 0) L.chunk_x = std::min(op->n[0], op->tune_chunk[dtype]);
+    return L;
+}
+
+// FP64 application of H to an FP32 block (Rayleigh-Ritz): 32 x 32 patches of
+// 512 threads measured 19% faster per point than 32 x 16 on the 96^3 grid;
+// launch overrides, which are tuned for the filter, do not apply
+StepLaunch choose_mixed_launch(const sparc_op *op, int ns)
+{
+    StepLaunch L;
+    L.shape = pick_taller(op, 1, 0.81);
+    L.chunk_x = default_chunk(op, L.shape, ns);
     return L;
 }
 
@@ -175,14 +197,9 @@ int launch_step(const sparc_op *op, int dtype, const void *yk, int64_t ldk, cons
 // workgroup count (one partial each) is fixed by the grid alone.
 static StepLaunch dot_launch(const sparc_op *op)
 {
-    const TileShape &s = kShapes[0];
-    const long long tiles = (long long)((op->n[1] + s.ty() - 1) / s.ty()) * ((op->n[2] + s.tz - 1) / s.tz);
-    const long long waves = tiles * (s.nt / 64);
-    long long nchunks = (8192 + waves - 1) / waves;
-    nchunks = std::max<long long>(1, std::min<long long>(nchunks, op->n[0] / 4));
     StepLaunch L;
     L.shape = 0;
-    L.chunk_x = (int)((op->n[0] + nchunks - 1) / nchunks);
+    L.chunk_x = default_chunk(op, 0, 1);
     return L;
 }
 
