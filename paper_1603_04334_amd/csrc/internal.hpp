@@ -141,11 +141,13 @@ int launch_gather_f32_to_f64(const sparc_op *op, const float *Y, int64_t ldy, in
 int launch_step_f32_to_f64(const sparc_op *op, const float *yk, int64_t ldk, double *out, int64_t ldo, int ns,
                            const StepCoef &c, const StepLaunch &L, hipStream_t stream);
 
-// H_loc v for one FP64 vector (N_d values, contiguous), also leaving
+// One launch for one FP64 vector v (N_d values, contiguous): out = H_loc v,
 // dot[b] = sum over workgroup b's points of v(x) (H_loc v)(x) for
-// b < step_dot_blocks(op)
+// b < step_dot_blocks(op), and the projector gather of v into part (as
+// launch_gather with ns = 1); the scatter follows separately
 long long step_dot_blocks(const sparc_op *op);
-int launch_step_dot_f64(const sparc_op *op, const double *v, double *out, double *dot, hipStream_t stream);
+int launch_lanczos_h_f64(const sparc_op *op, const double *v, double *out, double *dot, double *part,
+                         hipStream_t stream);
 
 // the full operator step: gather(yk), local step, scatter(alpha)
 int launch_h_step(const sparc_op *op, int dtype, const void *yk, int64_t ldk, const void *yprev, int64_t ldp,

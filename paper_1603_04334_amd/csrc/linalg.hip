@@ -721,8 +721,7 @@ int sparc_lanczos(const sparc_op *op, int32_t k, const double *v0, double *alpha
     for (int j = 0; j < k; ++j) {
         double *vj = V + (long long)j * n;
         // w = H v_j, with the two parts of alpha_j = v_j^T H v_j left as partials
-        if ((st = launch_gather(op, SPARC_F64, vj, n, 1, G, s))) return st;
-        if ((st = launch_step_dot_f64(op, vj, w, dotp, s))) return st;
+        if ((st = launch_lanczos_h_f64(op, vj, w, dotp, G, s))) return st;
         if ((st = launch_scatter(op, SPARC_F64, w, n, 1, G, 1.0, s))) return st;
         if (j + 1 == k) {
             hipLaunchKernelGGL(alpha_finish, dim3(1), tb, 0, s, (const double *)dotp, ndot, (const double *)G,

@@ -36,12 +36,28 @@
 //    smaller blocks stay cached from one step to the next.
 #include <type_traits>
 
+#include "nonlocal_kernel.hpp"
 #include "step_kernel.hpp"
 
 namespace sparc {
 
 const TileShape kShapes[kNumShapes] = {{32, 2, 256}, {32, 2, 512}, {32, 2, 768}, {64, 2, 256},
                                        {64, 2, 512}, {32, 4, 256}};
+
+// fixed-order workgroup sum of the per-thread products of a DOT launch
+template <typename T, int NT>
+__device__ __forceinline__ void store_dot(T v, T *dot, int b)
+{
+    __shared__ T red[NT / 64];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T t = red[0];
+        for (int i = 1; i < NT / 64; ++i) t += red[i];
+        dot[b] = t;
+    }
+}
 
 template <typename T, int TZ, int RY, int NT, bool PREV, bool STREAM, typename TI, bool DOT = false>
 __global__ void __launch_bounds__(NT) step_kernel(const StepArgs<T, TI> a)
@@ -50,19 +66,28 @@ __global__ void __launch_bounds__(NT) step_kernel(const StepArgs<T, TI> a)
     __shared__ T lds[2][K::SY * K::SZ];
     K k(a);
     k.run(blockIdx.x, lds);
-    if constexpr (DOT) {
-        // fixed-order workgroup sum of the per-thread products
-        __shared__ T red[NT / 64];
-        T v = k.dacc;
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            T t = red[0];
-            for (int i = 1; i < NT / 64; ++i) t += red[i];
-            a.dot[blockIdx.x] = t;
-        }
+    if constexpr (DOT) store_dot<T, NT>(k.dacc, a.dot, blockIdx.x);
+}
+
+// H v for one FP64 vector in one launch: the first ngather workgroups gather
+// the projections of v (atom i % natoms, split i / natoms, as the standalone
+// gather), the rest run the DOT step on 32 x 16 patches.  ngather is a
+// multiple of 8, so the step's XCD-aware index remap still sees the hardware
+// round-robin.
+__global__ void __launch_bounds__(256) lanczos_h_kernel(const StepArgs<double, double> a,
+                                                        const GatherArgs<double, double> g, int natoms, int ngather)
+{
+    if ((int)blockIdx.x < ngather) {
+        __shared__ double tile[4][16][16];
+        gather_item<double, double>(g, blockIdx.x % natoms, 0, blockIdx.x / natoms, tile);
+        return;
     }
+    using K = StepKernel<double, 32, 2, 256, false, false, double, true>;
+    __shared__ double lds[2][K::SY * K::SZ];
+    const int b = blockIdx.x - ngather;
+    K k(a);
+    k.run(b, lds);
+    store_dot<double, 256>(k.dacc, a.dot, b);
 }
 
 // split x so that about 8192 waves are in flight, keeping >= 4 planes per chunk
@@ -211,7 +236,8 @@ long long step_dot_blocks(const sparc_op *op)
            ((op->n[2] + s.tz - 1) / s.tz);
 }
 
-int launch_step_dot_f64(const sparc_op *op, const double *v, double *out, double *dot, hipStream_t stream)
+int launch_lanczos_h_f64(const sparc_op *op, const double *v, double *out, double *dot, double *part,
+                         hipStream_t stream)
 {
     const TileShape &s = kShapes[0];
     const StepLaunch L = dot_launch(op);
@@ -238,9 +264,18 @@ int launch_step_dot_f64(const sparc_op *op, const double *v, double *out, double
     a.alpha = 1.0;
     a.beta = 0.0;
     a.shift = 0.0;
+    GatherArgs<double, double> g;
+    g.Y = v;
+    g.ldy = op->nd;
+    g.ns = 1;
+    g.nproj_total = op->nproj_total;
+    g.atoms = op->d_atoms;
+    g.box_off = op->d_box_off;
+    g.chi = op->d_chi64;
+    g.part = part;
+    const int ngather = op->natoms * kGatherSplit;
     ProfScope prof(3, stream);
-    hipLaunchKernelGGL((step_kernel<double, 32, 2, 256, false, false, double, true>), dim3(a.nblocks), dim3(256), 0,
-                       stream, a);
+    hipLaunchKernelGGL(lanczos_h_kernel, dim3(ngather + a.nblocks), dim3(256), 0, stream, a, g, op->natoms, ngather);
     SPARC_HIP(hipGetLastError());
     return SPARC_OK;
 }
