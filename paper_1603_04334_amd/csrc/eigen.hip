@@ -8,20 +8,26 @@
 //      16 partial sums per entry in parallel, then C = X H_s X^T by two
 //      small products (each thread a 2 x 2 block);
 //   3. cyclic Jacobi on C with the round-robin (circle) ordering, so the n/2
-//      rotations of a round touch disjoint rows/columns.  A round is applied
-//      as one two-sided update: one wave computes the round's rotations, and
-//      the thread owning row pair k and column pair l maps the 2 x 2 block of
-//      C at (rows of k, columns of l) through the row rotation of k and then
-//      the column rotation of l, reading C from one LDS buffer and writing
-//      the other (two barriers per round, C read and written once).
+//      rotations of a round touch disjoint rows/columns; the pairs of every
+//      round are tabulated in LDS once.  A round is applied as one two-sided
+//      update: one wave computes the round's rotations, and the thread owning
+//      row pair k and column pair l maps the 2 x 2 block of C at (rows of k,
+//      columns of l) through the row rotation of k and then the column
+//      rotation of l, reading C from one LDS buffer and writing the other
+//      (two barriers per round, C read and written once); the same thread
+//      applies the column rotation of l to rows 2k, 2k+1 of Z, so the
+//      rotation is read once per thread.
 //      Sweeps stop when the off-diagonal mass is below 1e-30 of the total
 //      (relative 1e-15 in norm) or after max_sweeps;
 //   4. eigenvalues sorted ascending (stable), eigenvectors back-transformed
 //      q = X^T z so that Q^T M_s Q = I.
-// Rotation for the pair (p, q): tau = (c_qq - c_pp) / (2 c_pq),
-// t = sign(tau) / (|tau| + sqrt(1 + tau^2)), c = 1/sqrt(1 + t^2), s = t c;
-// rows and columns p, q are replaced by (c x_p - s x_q, s x_p + c x_q), which
-// zeroes c_pq.
+// Rotation for the pair (p, q): with tau = (c_qq - c_pp) / (2 c_pq), the
+// smaller root t = sign(tau) / (|tau| + sqrt(1 + tau^2)) of t^2 + 2 tau t = 1
+// gives c = 1/sqrt(1 + t^2), s = t c; rows and columns p, q are replaced by
+// (c x_p - s x_q, s x_p + c x_q), which zeroes c_pq.  Evaluated as
+// d = c_qq - c_pp, e = 2 c_pq, r = sqrt(d^2 + e^2), u = |d| + r,
+// c = u / sqrt(2 r u), s = sign(d) e / sqrt(2 r u) (the same t = sign(d) e / u,
+// with two square roots and one division on the dependent path).
 #include "internal.hpp"
 
 namespace sparc {
@@ -74,10 +80,15 @@ __device__ inline void jacobi_params(const double (*C)[kEigMax + 1], int p, int 
     c = 1.0;
     s = 0.0;
     if (q < n && C[p][q] != 0.0) {
-        const double tau = (C[q][q] - C[p][p]) / (2.0 * C[p][q]);
-        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-        c = 1.0 / sqrt(1.0 + t * t);
-        s = t * c;
+        const double e = 2.0 * C[p][q];
+        const double d = C[q][q] - C[p][p];
+        const double r = sqrt(d * d + e * e);
+        if (r > 0.0) {  // zero only if both underflow: leave the pair
+            const double u = fabs(d) + r;
+            const double inv = 1.0 / sqrt(2.0 * r * u);
+            c = u * inv;
+            s = (d >= 0.0 ? e : -e) * inv;
+        }
     }
 }
 
@@ -108,8 +119,8 @@ __global__ void __launch_bounds__(kEigThreads) small_sygv_kernel(const double *_
     __shared__ double L[kEigMax][kEigMax + 1];
     __shared__ double red[kEigThreads / 64];
     __shared__ double lam[kEigMax];
-    __shared__ double rc[kEigMax / 2], rs[kEigMax / 2];
-    __shared__ int rp[kEigMax / 2], rq[kEigMax / 2];
+    __shared__ double2 rcs[kEigMax / 2];                 // (c, s) of each pair of the round
+    __shared__ unsigned short rpq[kEigMax - 1][kEigMax / 2];  // p | q << 8 per round and pair
     __shared__ int rank[kEigMax];
     __shared__ int bad;
     const int tid = threadIdx.x;
@@ -186,21 +197,19 @@ __global__ void __launch_bounds__(kEigThreads) small_sygv_kernel(const double *_
     }
     __syncthreads();
 
-    // 3. cyclic Jacobi.  The work split is the same in every round, so each
-    // thread's block (pair k of rows, pair l of columns) and its entries of Z
-    // are fixed once here.
+    // 3. cyclic Jacobi.  The work split is the same in every round: thread
+    // (k, l) owns the block of row pair k and column pair l of C and rows
+    // 2k, 2k+1 of Z.
     const int half = np / 2;
+    for (int e = tid; e < (np - 1) * half; e += nt) {
+        int p, q;
+        round_pair(np, e / half, e % half, p, q);
+        rpq[e / half][e % half] = (unsigned short)(p | (q << 8));
+    }
+    __syncthreads();
     const bool has_blk = tid < half * half;
     const int bk = has_blk ? tid / half : 0, bl = has_blk ? tid % half : 0;
-    int zl[2], zi[2];
-    bool zok[2];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const int e = tid + u * kEigThreads;
-        zok[u] = e < half * n;
-        zl[u] = zok[u] ? e / n : 0;
-        zi[u] = zok[u] ? e % n : 0;
-    }
+    const int z0 = 2 * bk, z1 = 2 * bk + 1;
     int cur = 0;
     for (int sweep = 0; sweep < max_sweeps && n > 1; ++sweep) {
         const double(*A)[kEigMax + 1] = CB[cur];
@@ -218,19 +227,17 @@ __global__ void __launch_bounds__(kEigThreads) small_sygv_kernel(const double *_
             const double(*S)[kEigMax + 1] = CB[cur];
             double(*D)[kEigMax + 1] = CB[cur ^ 1];
             if (tid < half) {
-                int p, q;
-                round_pair(np, r, tid, p, q);
+                const int pq = rpq[r][tid];
                 double c, s;
-                jacobi_params(S, p, q, n, c, s);
-                rp[tid] = p;
-                rq[tid] = q;
-                rc[tid] = c;
-                rs[tid] = s;
+                jacobi_params(S, pq & 255, pq >> 8, n, c, s);
+                rcs[tid] = make_double2(c, s);
             }
             __syncthreads();
             if (has_blk) {
-                const int pk = rp[bk], qk = rq[bk], pl = rp[bl], ql = rq[bl];
-                const double ck = rc[bk], sk = rs[bk], cl = rc[bl], sl = rs[bl];
+                const int pqk = rpq[r][bk], pql = rpq[r][bl];
+                const int pk = pqk & 255, qk = pqk >> 8, pl = pql & 255, ql = pql >> 8;
+                const double2 rk = rcs[bk], rl = rcs[bl];
+                const double ck = rk.x, sk = rk.y, cl = rl.x, sl = rl.y;
                 const double a = S[pk][pl], b = S[pk][ql], d = S[qk][pl], g = S[qk][ql];
                 const double a1 = ck * a - sk * d, b1 = ck * b - sk * g;
                 const double d1 = sk * a + ck * d, g1 = sk * b + ck * g;
@@ -238,15 +245,16 @@ __global__ void __launch_bounds__(kEigThreads) small_sygv_kernel(const double *_
                 D[pk][ql] = sl * a1 + cl * b1;
                 D[qk][pl] = cl * d1 - sl * g1;
                 D[qk][ql] = sl * d1 + cl * g1;
-            }
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                if (!zok[u]) continue;
-                const int i = zi[u], pl = rp[zl[u]], ql = rq[zl[u]];
-                const double cl = rc[zl[u]], sl = rs[zl[u]];
-                const double za = Z[i][pl], zb = Z[i][ql];
-                Z[i][pl] = cl * za - sl * zb;
-                Z[i][ql] = sl * za + cl * zb;
+                if (z0 < n) {
+                    const double za = Z[z0][pl], zb = Z[z0][ql];
+                    Z[z0][pl] = cl * za - sl * zb;
+                    Z[z0][ql] = sl * za + cl * zb;
+                }
+                if (z1 < n) {
+                    const double za = Z[z1][pl], zb = Z[z1][ql];
+                    Z[z1][pl] = cl * za - sl * zb;
+                    Z[z1][ql] = sl * za + cl * zb;
+                }
             }
             cur ^= 1;
             __syncthreads();
