@@ -70,14 +70,11 @@ __device__ inline void block_segment(long long n, long long &beg, long long &end
 
 // block-level partial inner products: partial[b*(nv+1) + i] = sum over block
 // b's points of V_i(x) w(x) for i < nv, and of w(x)^2 for i = nv.  Groups of
-// 8 vectors per pass over the segment.  (run != nullptr and *run == 0:
-// nothing to do)
-__global__ void __launch_bounds__(256) multidot_kernel(const double *__restrict__ V, long long ldv, int nv,
-                                                       const double *__restrict__ w, long long n,
-                                                       double *__restrict__ partial, const int *run)
+// 8 vectors per pass over the segment.
+__device__ __forceinline__ void multidot_block(const double *__restrict__ V, long long ldv, int nv,
+                                               const double *__restrict__ w, long long n,
+                                               double *__restrict__ partial, double *red)
 {
-    if (run && !*run) return;
-    __shared__ double red[4];
     long long beg, end;
     block_segment(n, beg, end);
     double *out = partial + (long long)blockIdx.x * (nv + 1);
@@ -112,6 +109,14 @@ __global__ void __launch_bounds__(256) multidot_kernel(const double *__restrict_
             if (threadIdx.x == 0 && i0 + u <= nv) out[i0 + u] = t;
         }
     }
+}
+
+__global__ void __launch_bounds__(256) multidot_kernel(const double *__restrict__ V, long long ldv, int nv,
+                                                       const double *__restrict__ w, long long n,
+                                                       double *__restrict__ partial)
+{
+    __shared__ double red[4];
+    multidot_block(V, ldv, nv, w, n, partial, red);
 }
 
 // out[i] = sum over the block partials of entry i (stride per block), one
@@ -241,54 +246,70 @@ __global__ void __launch_bounds__(256) lanczos_3term(double *w, const double *__
 // w = row j, w'' = row j-1, and w'_j = eps1 ||T|| / beta_j.  The new vector
 // is orthogonalised against the whole basis when an estimate passes sqrt(eps)
 // and, after that, once more on the next step; its row then restarts at eps1.
-// state[0]: orthogonalise the vector of this step; state[1]: owe the next one.
-// The kernel first finishes beta_j = sqrt(sum of the block partials of |w|^2)
-// (the same fixed order as finish_sums) and stores it.
-__global__ void __launch_bounds__(256) omega_kernel(const double *alpha, double *beta, int j, double eps1,
-                                                    const double *Wp, const double *Wc, double *Wn, int *state,
-                                                    double *anorm, const double *partial)
+//
+// Every workgroup of this kernel finishes beta_j = sqrt(sum of the block
+// partials of |w|^2) (the same fixed order as finish_sums) and evaluates the
+// recurrence and the decision itself, bitwise identically; workgroup 0 stores
+// beta_j, row j+1, ||T|| (anorm[j+1]), full[j] (orthogonalise now) and
+// owed[j+1] (orthogonalise the next vector too).  Per-step slots keep the
+// values read (owed[j], anorm[j]) apart from those written.  When the
+// vector is to be orthogonalised, the workgroups go on to the inner products
+// V^T w with v_0 .. v_j (partials as multidot_kernel); otherwise they exit.
+__global__ void __launch_bounds__(256) omega_dots_kernel(const double *alpha, double *beta, int j, double eps1,
+                                                         const double *Wp, const double *Wc, double *Wn,
+                                                         int *owed, int *full, double *anorm,
+                                                         const double *npart, const double *__restrict__ V,
+                                                         long long ldv, const double *__restrict__ w, long long n,
+                                                         double *__restrict__ partial)
 {
     __shared__ double red[4];
-    const double bj = sqrt(sum_partials(partial, 1, 0, red));
-    if (threadIdx.x >= 64) return;
-    const int lane = threadIdx.x;
-    if (lane == 0) beta[j] = bj;
-    const double aj = alpha[j], bjm = j > 0 ? beta[j - 1] : 0.0;
-    const double an = fmax(*anorm, fabs(aj) + bj + bjm);
-    double mx = 0.0;
-    for (int i = lane; i < j; i += 64) {
-        double t = beta[i] * Wc[i + 1] + (alpha[i] - aj) * Wc[i] - bjm * Wp[i];
-        if (i > 0) t += beta[i - 1] * Wc[i - 1];
-        t += copysign(eps1 * (beta[i] + bj), t);
-        mx = fmax(mx, fabs(t / bj));
+    __shared__ int sfull;
+    const double bj = sqrt(sum_partials(npart, 1, 0, red));
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const double aj = alpha[j], bjm = j > 0 ? beta[j - 1] : 0.0;
+        const double an = fmax(anorm[j], fabs(aj) + bj + bjm);
+        double mx = 0.0;
+        for (int i = lane; i < j; i += 64) {
+            double t = beta[i] * Wc[i + 1] + (alpha[i] - aj) * Wc[i] - bjm * Wp[i];
+            if (i > 0) t += beta[i - 1] * Wc[i - 1];
+            t += copysign(eps1 * (beta[i] + bj), t);
+            mx = fmax(mx, fabs(t / bj));
+        }
+        for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+        const double dj = eps1 * an / bj;
+        const bool owe = owed[j] != 0;
+        const bool f = owe || fmax(mx, dj) > 1.4901161193847656e-08;  // sqrt(eps)
+        if (blockIdx.x == 0) {
+            // second pass for the row values (cheap, avoids holding them across the reduction)
+            for (int i = lane; i < j; i += 64) {
+                double t = beta[i] * Wc[i + 1] + (alpha[i] - aj) * Wc[i] - bjm * Wp[i];
+                if (i > 0) t += beta[i - 1] * Wc[i - 1];
+                t += copysign(eps1 * (beta[i] + bj), t);
+                Wn[i] = f ? eps1 : t / bj;
+            }
+            if (lane == 0) {
+                beta[j] = bj;
+                Wn[j] = f ? eps1 : dj;
+                Wn[j + 1] = 1.0;
+                anorm[j + 1] = an;
+                full[j] = f ? 1 : 0;
+                owed[j + 1] = (f && !owe) ? 1 : 0;
+            }
+        }
+        if (lane == 0) sfull = f ? 1 : 0;
     }
-    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
-    const double dj = eps1 * an / bj;
-    const bool owed = state[1] != 0;
-    const bool full = owed || fmax(mx, dj) > 1.4901161193847656e-08;  // sqrt(eps)
-    // second pass for the row values (cheap, avoids holding them across the reduction)
-    for (int i = lane; i < j; i += 64) {
-        double t = beta[i] * Wc[i + 1] + (alpha[i] - aj) * Wc[i] - bjm * Wp[i];
-        if (i > 0) t += beta[i - 1] * Wc[i - 1];
-        t += copysign(eps1 * (beta[i] + bj), t);
-        Wn[i] = full ? eps1 : t / bj;
-    }
-    if (lane == 0) {
-        Wn[j] = full ? eps1 : dj;
-        Wn[j + 1] = 1.0;
-        *anorm = an;
-        state[0] = full ? 1 : 0;
-        state[1] = (full && !owed) ? 1 : 0;
-    }
+    __syncthreads();
+    if (!sfull) return;
+    multidot_block(V, ldv, j + 1, w, n, partial, red);
 }
 
-// state = {0, 0}, anorm = 0, rows j = 0 (1 at i = 0) and j = -1 (zero)
-__global__ void omega_init(double *rows, int len, int *state, double *anorm)
+// rows j = 0 (1 at i = 0) and j = -1 (zero); owed[0] = 0, anorm[0] = 0
+__global__ void omega_init(double *rows, int len, int *owed, double *anorm)
 {
     for (int i = threadIdx.x; i < 3 * len; i += blockDim.x) rows[i] = (i == 0) ? 1.0 : 0.0;
     if (threadIdx.x == 0) {
-        state[0] = 0;
-        state[1] = 0;
+        owed[0] = 0;
         *anorm = 0.0;
     }
 }
@@ -667,14 +688,14 @@ size_t sparc_lanczos_workspace_bytes(const sparc_op *op, int32_t k)
     b += align_up((size_t)(4 * k + 8) * sizeof(double));                  // alpha, beta, coeff, norm
     b += align_up((size_t)kRedBlocks * (k + 3) * sizeof(double));         // block partial sums
     b += align_up((size_t)step_dot_blocks(op) * sizeof(double));           // v^T H_loc v partials
-    b += align_up((size_t)(3 * (k + 2) + 1) * sizeof(double));            // omega rows, ||T|| estimate
-    b += align_up(2 * sizeof(int));                                         // reorthogonalisation state
+    b += align_up((size_t)(3 * (k + 2) + k + 1) * sizeof(double));        // omega rows, ||T|| per step
+    b += align_up((size_t)(2 * k + 1) * sizeof(int));                       // reorthogonalisation flags per step
     return b;
 }
 
 // Lanczos with partial re-orthogonalisation: w = H v_j, alpha_j = v_j^T H v_j,
 // w -= alpha_j v_j + beta_{j-1} v_{j-1}, beta_j = |w|; when the omega
-// recurrence (omega_kernel) estimates a loss of orthogonality beyond sqrt(eps),
+// recurrence (omega_dots_kernel) estimates a loss of orthogonality beyond sqrt(eps),
 // one classical Gram-Schmidt pass against v_0 .. v_j (c = V^T w, w -= V c) and
 // a new beta_j; v_{j+1} = w / beta_j.  Every step is enqueued without a host
 // round trip: the conditional pass reads its flag on the device.
@@ -704,19 +725,19 @@ int sparc_lanczos(const sparc_op *op, int32_t k, const double *v0, double *alpha
     const int ndot = (int)step_dot_blocks(op);
     p += align_up((size_t)ndot * sizeof(double));
     double *rows = (double *)p;  // three rows of orthogonality estimates, k + 2 entries each
-    double *d_anorm = rows + 3 * (k + 2);
-    p += align_up((size_t)(3 * (k + 2) + 1) * sizeof(double));
-    int *d_state = (int *)p;
+    double *d_anorm = rows + 3 * (k + 2);  // ||T|| estimate after each step (k + 1)
+    p += align_up((size_t)(3 * (k + 2) + k + 1) * sizeof(double));
+    int *d_owed = (int *)p;     // k + 1: orthogonalise the vector of step j regardless
+    int *d_full = d_owed + k + 1;  // k: the vector of step j is orthogonalised
     double *w = V + (long long)k * n;
     const double eps1 = 0.5 * std::sqrt((double)n) * 2.220446049250313e-16;
 
     const dim3 rg(kRedBlocks), tb(256);
-    const int *always = nullptr;
     int st;
-    hipLaunchKernelGGL(omega_init, dim3(1), tb, 0, s, rows, k + 2, d_state, d_anorm);
+    hipLaunchKernelGGL(omega_init, dim3(1), tb, 0, s, rows, k + 2, d_owed, d_anorm);
     // V_0 = v0 / |v0|
-    hipLaunchKernelGGL(multidot_kernel, rg, tb, 0, s, v0, (long long)n, 0, v0, n, npart, always);
-    hipLaunchKernelGGL(scale_by_norm, rg, tb, 0, s, V, v0, d_norm, (const double *)npart, always, n);
+    hipLaunchKernelGGL(multidot_kernel, rg, tb, 0, s, v0, (long long)n, 0, v0, n, npart);
+    hipLaunchKernelGGL(scale_by_norm, rg, tb, 0, s, V, v0, d_norm, (const double *)npart, (const int *)nullptr, n);
     const int nproj = op->nproj_total;
     for (int j = 0; j < k; ++j) {
         double *vj = V + (long long)j * n;
@@ -732,17 +753,18 @@ int sparc_lanczos(const sparc_op *op, int32_t k, const double *v0, double *alpha
         hipLaunchKernelGGL(lanczos_3term, rg, tb, 0, s, w, (const double *)vj, (const double *)(vj - (j > 0 ? n : 0)),
                            (const double *)dotp, ndot, (const double *)G, (const double *)op->d_hg64, nproj,
                            d_alpha + j, (const double *)(j > 0 ? d_beta + j - 1 : nullptr), n, npart);
-        // beta_j and the orthogonality estimates; when needed, one classical
-        // Gram-Schmidt pass against v_0 .. v_j, whose new |w|^2 partials the
-        // scaling kernel finishes into beta_j
+        // beta_j, the orthogonality estimates and, when they ask for it, the
+        // inner products of one classical Gram-Schmidt pass against
+        // v_0 .. v_j, whose new |w|^2 partials the scaling kernel finishes
+        // into beta_j
         const double *Wc = rows + (size_t)(j % 3) * (k + 2);
         const double *Wp = rows + (size_t)((j + 2) % 3) * (k + 2);
         double *Wn = rows + (size_t)((j + 1) % 3) * (k + 2);
-        hipLaunchKernelGGL(omega_kernel, dim3(1), tb, 0, s, (const double *)d_alpha, d_beta, j, eps1, Wp, Wc, Wn,
-                           d_state, d_anorm, (const double *)npart);
         const int nv = j + 1;
-        const int *full = d_state;
-        hipLaunchKernelGGL(multidot_kernel, rg, tb, 0, s, V, (long long)n, nv, w, n, partial, full);
+        const int *full = d_full + j;
+        hipLaunchKernelGGL(omega_dots_kernel, rg, tb, 0, s, (const double *)d_alpha, d_beta, j, eps1, Wp, Wc, Wn,
+                           d_owed, d_full, d_anorm, (const double *)npart, (const double *)V, (long long)n,
+                           (const double *)w, n, partial);
         hipLaunchKernelGGL(finish_sums, dim3(nv), tb, 0, s, (const double *)partial, nv + 1, d_coeff, nullptr, -1, 0,
                            full);
         hipLaunchKernelGGL(orth_apply_norm, rg, tb, 0, s, w, V, (long long)n, nv, d_coeff, n, npart, full);
