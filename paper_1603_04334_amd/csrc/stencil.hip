@@ -25,9 +25,15 @@
 //    plane; the remaining y- and z-neighbours come from there.  Halo values
 //    belong to neighbouring patches and are served from L2 when neighbours
 //    run on the same XCD, which the workgroup-index remap arranges.
-//  * All global loads are unconditional (out-of-grid addresses are clamped
-//    and the value replaced by zero) and are issued two planes ahead, so each
-//    wait only covers loads issued one full plane earlier.
+//  * All global accesses are unconditional raw buffer loads and stores
+//    through per-plane descriptors: a point or plane outside the grid falls
+//    outside the descriptor's range, so it loads zero and its store is
+//    dropped, without selects or 64-bit address arithmetic.  Loads are issued
+//    two planes ahead, so each wait only covers loads issued one full plane
+//    earlier.
+//  * Patch shapes: 32 x 16 with 256 threads (FP64), 32 x 48 with 768 threads
+//    (FP32 filter: fewer halo re-reads), 32 x 32 with 512 threads (FP64 H on
+//    an FP32 block); sparc_autotune may override the filter's choice.
 //  * yprev is read pointwise and out may alias it: a thread reads yprev(x)
 //    one plane before it writes out(x), and no other thread touches x.
 //  * When the three blocks of a step exceed the last-level (Infinity) cache,
