@@ -874,6 +874,10 @@ int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_
         if (rocsolver_dsygvd(hb, rocblas_eform_ax, evec ? rocblas_evect_original : rocblas_evect_none,
                              rocblas_fill_upper, ns, Hs, ns, Ms, ns, D, E, info) != rocblas_status_success)
             return fail(SPARC_E_HIP, "rocsolver_dsygvd failed");
+        // the library reports failures through its status; a HIP error it met
+        // and handled internally must not be charged to this thread's next
+        // launch check
+        (void)hipGetLastError();
     }
     int hinfo = 0;
     SPARC_HIP(hipMemcpyAsync(theta, D, ns * sizeof(double), hipMemcpyDeviceToHost, s));
