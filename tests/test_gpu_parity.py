@@ -358,3 +358,21 @@ def test_large_sampled_columns():
     assert e32 <= TOL32
     one = host(op.cheb_filter(X[cols[1]:cols[1] + 1].contiguous(), c.m, a0, a, b))
     assert np.array_equal(one[0], got[1])
+
+
+@pytest.mark.parametrize("ns,nd", [(1, 700), (7, 5000), (33, 3089), (64, 5000), (64, 131)])
+def test_rotation_f32_blocks(ns, nd):
+    # FP32 blocks of at most 64 columns take the matrix-core kernel (FP32
+    # accumulation): against the oracle's FP64 product of the same FP32 values,
+    # with padded leading dimension and a ragged tail of points
+    binding = _b()
+    rng = np.random.default_rng(1000 + ns)
+    Y = inputs.round_to_f32(rng.standard_normal((ns, nd)))
+    Q, _ = np.linalg.qr(rng.standard_normal((ns, ns)))
+    Ypad = torch.zeros((ns, nd + 5), dtype=torch.float32, device="cuda")
+    Ypad[:, :nd] = dev(Y, torch.float32)
+    R = host(binding.rotate(Ypad[:, :nd], dev(Q.T)))
+    ref = oracle.rotate(Y, Q)
+    err = rel_err(R, ref)
+    print("FP32 rotation ns", ns, "nd", nd, "max per-column relative error", err)
+    assert err <= 2e-6
