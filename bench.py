@@ -327,17 +327,22 @@ def serve_measure(rates, nrequests, workers):
 
 
 def cpu_baseline(case, cl):
+    """The C oracle's FP64 filter on the host, in groups of 8 orbitals of the
+    same cluster until about 10 s of work (or all orbitals) are done."""
     import oracle
     from paper_1603_04334_amd import inputs
-    cols = list(range(8))
-    X = inputs.orbitals(cl.nd, case.ns, case.seed, cols=cols)
     a0, a, b = -2.0, 3.0, oracle.upper_bound(cl)
-    t0 = time.perf_counter()
-    oracle.cheb_filter(cl, X, case.m, a0, a, b)
-    dt = time.perf_counter() - t0
-    return {"value": len(cols) * cl.nd * case.m / dt, "unit": "orbital*gridpts/s", "cores": oracle.num_threads(),
+    done, dt = 0, 0.0
+    while done < case.ns and dt < 10.0:
+        cols = list(range(done, min(case.ns, done + 8)))
+        X = inputs.orbitals(cl.nd, case.ns, case.seed, cols=cols)
+        t0 = time.perf_counter()
+        oracle.cheb_filter(cl, X, case.m, a0, a, b)
+        dt += time.perf_counter() - t0
+        done += len(cols)
+    return {"value": done * cl.nd * case.m / dt, "unit": "orbital*gridpts/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"FP64 C oracle Chebyshev filter (degree {case.m}) of {len(cols)} of the {case.ns} "
+            "sample": f"FP64 C oracle Chebyshev filter (degree {case.m}) of {done} of the {case.ns} "
                       f"orbitals of the same cluster, {dt:.1f} s on the host"}
 
 
