@@ -145,10 +145,18 @@ def timed(fn, steps, warmup):
 
 
 def alg_bytes_per_step_launch(case, cl, s):
-    """Algorithmic HBM bytes of one recurrence-step launch of the fused
-    kernel: read Y_k and Y_{k-1}, write Y_{k+1} (s bytes per orbital*gridpoint
-    each) and read V_eff once (s bytes per gridpoint)."""
-    return 3 * s * cl.nd * case.ns + s * cl.nd
+    """Algorithmic HBM bytes of one recurrence-step launch, which runs the
+    fused step and the projector gather of the same Y_k: read Y_k and Y_{k-1},
+    write Y_{k+1} (s bytes per orbital*gridpoint each), read V_eff once (s
+    bytes per gridpoint); the gather reads Y_k at the cube points again (s per
+    orbital*cube point), chi once per group of 16 orbitals (s per cube point
+    and projector) and writes its 8 split partials (s per projector and
+    orbital each)."""
+    cube = sum(int(np.prod(a.ext)) for a in cl.atoms)
+    chi = sum(int(np.prod(a.ext)) * a.nproj for a in cl.atoms)
+    ncb = (case.ns + 15) // 16
+    gather = s * (case.ns * cube + ncb * chi + 8 * cl.nproj_total * case.ns)
+    return 3 * s * cl.nd * case.ns + s * cl.nd + gather
 
 
 def batch_measure(reps=5, nclusters=64):
@@ -410,7 +418,7 @@ def main():
         "filter_only": {"value": updates / t_filter, "ms": t_filter * 1e3},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "step_kernel (fused stencil + local potential + recurrence, with Y_{k-1})",
+                     "kernel": "step_gather_kernel (fused stencil + local potential + recurrence with Y_{k-1}, and the projector gather of Y_k)",
                      "launches": n_launch, "avg_launch_us": avg_s * 1e6,
                      "alg_bytes_per_launch": alg},
         "gather_kernel": {"launches": n_g, "avg_launch_us": ms_g / max(n_g, 1) * 1e3},

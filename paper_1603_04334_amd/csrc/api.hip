@@ -103,8 +103,7 @@ int launch_h_step(const sparc_op *op, int dtype, const void *yk, int64_t ldk, co
                   hipStream_t stream)
 {
     int st;
-    if ((st = launch_gather(op, dtype, yk, ldk, ns, part, stream))) return st;
-    if ((st = launch_step(op, dtype, yk, ldk, yprev, ldp, out, ldo, ns, c, L, stream))) return st;
+    if ((st = launch_step_gather(op, dtype, yk, ldk, yprev, ldp, out, ldo, ns, part, c, L, stream))) return st;
     return launch_scatter(op, dtype, out, ldo, ns, part, c.alpha, stream);
 }
 

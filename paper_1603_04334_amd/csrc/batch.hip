@@ -124,7 +124,7 @@ __device__ __forceinline__ void do_gather(const BatchClusterDev &c, int k, int l
     const int atom = local / kGatherSplit, ks = local % kGatherSplit;
 #pragma unroll 1
     for (int cb = 0; cb < c.ncb; ++cb) {
-        gather_item<T>(g, atom, cb, ks, (T(*)[16][16])smem);
+        gather_item<T>(g, atom, cb, ks, (T(*)[16][16])smem, threadIdx.x);
         __syncthreads();
     }
 }

@@ -149,6 +149,11 @@ long long step_dot_blocks(const sparc_op *op);
 int launch_lanczos_h_f64(const sparc_op *op, const double *v, double *out, double *dot, double *part,
                          hipStream_t stream);
 
+// the projector gather of yk into part and the local step in one launch
+int launch_step_gather(const sparc_op *op, int dtype, const void *yk, int64_t ldk, const void *yprev, int64_t ldp,
+                       void *out, int64_t ldo, int ns, void *part, const StepCoef &c, const StepLaunch &L,
+                       hipStream_t stream);
+
 // the full operator step: gather(yk), local step, scatter(alpha)
 int launch_h_step(const sparc_op *op, int dtype, const void *yk, int64_t ldk, const void *yprev, int64_t ldp,
                   void *out, int64_t ldo, int ns, void *part, const StepCoef &c, const StepLaunch &L,

@@ -30,7 +30,7 @@ template <typename T, typename TI>
 __global__ void __launch_bounds__(256) gather_kernel(const GatherArgs<T, TI> g)
 {
     __shared__ T tile[4][16][16];
-    gather_item<T, TI>(g, blockIdx.x, blockIdx.y, blockIdx.z, tile);
+    gather_item<T, TI>(g, blockIdx.x, blockIdx.y, blockIdx.z, tile, threadIdx.x);
 }
 
 template <typename T>

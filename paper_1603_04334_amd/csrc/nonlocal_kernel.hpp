@@ -53,8 +53,11 @@ __device__ inline int acc_row(int lane, int r)
 
 constexpr int kGatherUnroll = 8;  // groups of 4 points per wave per batch
 
+// tid: this thread's index within the 256 threads (4 waves) that run the
+// item; the item has one workgroup barrier
 template <typename T, typename TI = T>
-__device__ __forceinline__ void gather_item(const GatherArgs<T, TI> &g, int atom, int cb, int ks, T (*tile)[16][16])
+__device__ __forceinline__ void gather_item(const GatherArgs<T, TI> &g, int atom, int cb, int ks, T (*tile)[16][16],
+                                            int tid)
 {
     const int c0 = cb * 16;
     const AtomDev A = g.atoms[atom];
@@ -62,8 +65,8 @@ __device__ __forceinline__ void gather_item(const GatherArgs<T, TI> &g, int atom
     const int chunk = (nbox + kGatherSplit - 1) / kGatherSplit;
     const int k0 = min(nbox, ks * chunk);
     const int k1 = min(nbox, k0 + chunk);
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
     const int i = lane & 15;
     const int k = lane >> 4;
     const int col = c0 + i;
@@ -99,8 +102,7 @@ __device__ __forceinline__ void gather_item(const GatherArgs<T, TI> &g, int atom
 #pragma unroll
     for (int r = 0; r < 4; ++r) tile[wave][acc_row<T>(lane, r)][lane & 15] = acc[r];
     __syncthreads();
-    const int t = threadIdx.x;
-    const int row = t >> 4, pj = t & 15;
+    const int row = tid >> 4, pj = tid & 15;
     const int cc = c0 + row;
     if (cc < g.ns && pj < A.nproj) {
         const T s = ((tile[0][row][pj] + tile[1][row][pj]) + tile[2][row][pj]) + tile[3][row][pj];

@@ -75,6 +75,34 @@ __global__ void __launch_bounds__(NT) step_kernel(const StepArgs<T, TI> a)
     if constexpr (DOT) store_dot<T, NT>(k.dacc, a.dot, blockIdx.x);
 }
 
+// One filter step with the projector gather of the same Y_k in one launch:
+// the first ngb workgroups run NT/256 gather items each, 256 threads apiece
+// (item = atom + natoms (column group + ncb split), the standalone gather's
+// grid order; a group past the last item only joins the item's barrier); the
+// rest run the step.  ngb is a multiple of 8, so the step's XCD-aware index
+// remap still sees the hardware round-robin.
+template <typename T, int TZ, int RY, int NT, bool PREV, bool STREAM>
+__global__ void __launch_bounds__(NT) step_gather_kernel(const StepArgs<T, T> a, const GatherArgs<T, T> g,
+                                                         int natoms, int ncb, int nitems, int ngb)
+{
+    if ((int)blockIdx.x < ngb) {
+        constexpr int G = NT / 256;
+        __shared__ T tile[G][4][16][16];
+        const int sub = threadIdx.x >> 8;
+        const int item = blockIdx.x * G + sub;
+        if (item < nitems)
+            gather_item<T, T>(g, item % natoms, (item / natoms) % ncb, item / (natoms * ncb), tile[sub],
+                              threadIdx.x & 255);
+        else
+            __syncthreads();
+        return;
+    }
+    using K = StepKernel<T, TZ, RY, NT, PREV, STREAM, T>;
+    __shared__ T lds[2][K::SY * K::SZ];
+    K k(a);
+    k.run(blockIdx.x - ngb, lds);
+}
+
 // H v for one FP64 vector in one launch: the first ngather workgroups gather
 // the projections of v (atom i % natoms, split i / natoms, as the standalone
 // gather), the rest run the DOT step on 32 x 16 patches.  ngather is a
@@ -85,7 +113,7 @@ __global__ void __launch_bounds__(256) lanczos_h_kernel(const StepArgs<double, d
 {
     if ((int)blockIdx.x < ngather) {
         __shared__ double tile[4][16][16];
-        gather_item<double, double>(g, blockIdx.x % natoms, 0, blockIdx.x / natoms, tile);
+        gather_item<double, double>(g, blockIdx.x % natoms, 0, blockIdx.x / natoms, tile, threadIdx.x);
         return;
     }
     using K = StepKernel<double, 32, 2, 256, false, false, double, true>;
@@ -142,9 +170,36 @@ StepLaunch choose_mixed_launch(const sparc_op *op, int ns)
     return L;
 }
 
+// gather launch data for launch_typed (ngb == 0: plain step)
+template <typename T>
+struct GatherPlan {
+    GatherArgs<T, T> g;
+    int natoms = 0, ncb = 0, nitems = 0, ngb = 0;
+};
+
 template <typename T, int TZ, int RY, int NT, typename TI>
-static int launch_typed(const StepArgs<T, TI> &a, bool prev, bool strm, hipStream_t stream)
+static int launch_typed(const StepArgs<T, TI> &a, bool prev, bool strm, hipStream_t stream,
+                        const GatherPlan<T> *gp = nullptr)
 {
+    if constexpr (std::is_same<T, TI>::value) {
+        if (gp && gp->ngb > 0) {
+            const dim3 grid(a.nblocks + gp->ngb), blk(NT);
+#define SPARC_SG(P, S)                                                                                           \
+    hipLaunchKernelGGL((step_gather_kernel<T, TZ, RY, NT, P, S>), grid, blk, 0, stream, a, gp->g, gp->natoms, \
+                       gp->ncb, gp->nitems, gp->ngb)
+            if (prev && strm)
+                SPARC_SG(true, true);
+            else if (prev)
+                SPARC_SG(true, false);
+            else if (strm)
+                SPARC_SG(false, true);
+            else
+                SPARC_SG(false, false);
+#undef SPARC_SG
+            SPARC_HIP(hipGetLastError());
+            return SPARC_OK;
+        }
+    }
     const dim3 g(a.nblocks), b(NT);
     if constexpr (std::is_same<T, TI>::value) {
         if (prev && strm)
@@ -165,7 +220,7 @@ static int launch_typed(const StepArgs<T, TI> &a, bool prev, bool strm, hipStrea
 template <typename T, typename TI = T>
 static int launch_step_t(const sparc_op *op, const void *yk, int64_t ldk, const void *yprev, int64_t ldp,
                          void *out, int64_t ldo, int ns, const StepCoef &c, const StepLaunch &L,
-                         hipStream_t stream, const T *veff)
+                         hipStream_t stream, const T *veff, void *part = nullptr, const T *chi = nullptr)
 {
     const TileShape &s = kShapes[L.shape];
     StepArgs<T, TI> a;
@@ -196,14 +251,32 @@ static int launch_step_t(const sparc_op *op, const void *yk, int64_t ldk, const 
     a.shift = (T)c.shift;
     // blocks the last-level cache cannot keep between steps are streamed
     const bool strm = (double)op->nd * ns * (2 * sizeof(T) + sizeof(TI)) > kStreamBytes;
+    GatherPlan<T> gp;
+    if (part && op->natoms > 0) {
+        if ((long long)(ns + 15) / 16 > 65535) return fail(SPARC_E_SHAPE, "too many columns for one gather launch");
+        gp.g.Y = (const T *)yk;
+        gp.g.ldy = ldk;
+        gp.g.ns = ns;
+        gp.g.nproj_total = op->nproj_total;
+        gp.g.atoms = op->d_atoms;
+        gp.g.box_off = op->d_box_off;
+        gp.g.chi = chi;
+        gp.g.part = (T *)part;
+        gp.natoms = op->natoms;
+        gp.ncb = (ns + 15) / 16;
+        gp.nitems = op->natoms * gp.ncb * kGatherSplit;
+        const int per = kShapes[L.shape].nt / 256;
+        gp.ngb = ((gp.nitems + per - 1) / per + 7) / 8 * 8;
+        if ((long long)a.nblocks + gp.ngb > 0x7fffffffLL) return fail(SPARC_E_SHAPE, "too many workgroups for one launch");
+    }
     ProfScope prof(prev ? 0 : 3, stream);
     switch (L.shape) {
-        case 0: return launch_typed<T, 32, 2, 256, TI>(a, prev, strm, stream);
-        case 1: return launch_typed<T, 32, 2, 512, TI>(a, prev, strm, stream);
-        case 2: return launch_typed<T, 32, 2, 768, TI>(a, prev, strm, stream);
-        case 3: return launch_typed<T, 64, 2, 256, TI>(a, prev, strm, stream);
-        case 4: return launch_typed<T, 64, 2, 512, TI>(a, prev, strm, stream);
-        case 5: return launch_typed<T, 32, 4, 256, TI>(a, prev, strm, stream);
+        case 0: return launch_typed<T, 32, 2, 256, TI>(a, prev, strm, stream, &gp);
+        case 1: return launch_typed<T, 32, 2, 512, TI>(a, prev, strm, stream, &gp);
+        case 2: return launch_typed<T, 32, 2, 768, TI>(a, prev, strm, stream, &gp);
+        case 3: return launch_typed<T, 64, 2, 256, TI>(a, prev, strm, stream, &gp);
+        case 4: return launch_typed<T, 64, 2, 512, TI>(a, prev, strm, stream, &gp);
+        case 5: return launch_typed<T, 32, 4, 256, TI>(a, prev, strm, stream, &gp);
     }
     return fail(SPARC_E_ARG, "unknown tile shape");
 }
@@ -213,6 +286,17 @@ int launch_step_f32_to_f64(const sparc_op *op, const float *yk, int64_t ldk, dou
 {
     if (c.has_prev) return fail(SPARC_E_ARG, "mixed-precision step has no Y_{k-1} term");
     return launch_step_t<double, float>(op, yk, ldk, nullptr, 0, out, ldo, ns, c, L, stream, op->d_veff64);
+}
+
+int launch_step_gather(const sparc_op *op, int dtype, const void *yk, int64_t ldk, const void *yprev, int64_t ldp,
+                       void *out, int64_t ldo, int ns, void *part, const StepCoef &c, const StepLaunch &L,
+                       hipStream_t stream)
+{
+    if (dtype == SPARC_F64)
+        return launch_step_t<double>(op, yk, ldk, yprev, ldp, out, ldo, ns, c, L, stream, op->d_veff64, part,
+                                     op->d_chi64);
+    return launch_step_t<float>(op, yk, ldk, yprev, ldp, out, ldo, ns, c, L, stream, op->d_veff32, part,
+                                op->d_chi32);
 }
 
 int launch_step(const sparc_op *op, int dtype, const void *yk, int64_t ldk, const void *yprev, int64_t ldp,
