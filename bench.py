@@ -357,7 +357,7 @@ def cpu_baseline(case, cl):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "bench.py measures one GPU only; runs on several GPUs are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
