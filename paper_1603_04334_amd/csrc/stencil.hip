@@ -76,20 +76,20 @@ __global__ void __launch_bounds__(NT) step_kernel(const StepArgs<T, TI> a)
 }
 
 // One filter step with the projector gather of the same Y_k in one launch:
-// the first ngb workgroups run NT/256 gather items each, 256 threads apiece
-// (item = atom + natoms (column group + ncb split), the standalone gather's
-// grid order; a group past the last item only joins the item's barrier); the
-// rest run the step.  ngb is a multiple of 8, so the step's XCD-aware index
-// remap still sees the hardware round-robin.
+// the first a.nblocks workgroups run the step (its XCD-aware index remap sees
+// the hardware round-robin unchanged), the last ngb run NT/256 gather items
+// each, 256 threads apiece (item = atom + natoms (column group + ncb split),
+// the standalone gather's grid order; a group past the last item only joins
+// the item's barrier), filling CUs as the step's workgroups drain.
 template <typename T, int TZ, int RY, int NT, bool PREV, bool STREAM>
 __global__ void __launch_bounds__(NT) step_gather_kernel(const StepArgs<T, T> a, const GatherArgs<T, T> g,
-                                                         int natoms, int ncb, int nitems, int ngb)
+                                                         int natoms, int ncb, int nitems)
 {
-    if ((int)blockIdx.x < ngb) {
+    if ((int)blockIdx.x >= a.nblocks) {
         constexpr int G = NT / 256;
         __shared__ T tile[G][4][16][16];
         const int sub = threadIdx.x >> 8;
-        const int item = blockIdx.x * G + sub;
+        const int item = ((int)blockIdx.x - a.nblocks) * G + sub;
         if (item < nitems)
             gather_item<T, T>(g, item % natoms, (item / natoms) % ncb, item / (natoms * ncb), tile[sub],
                               threadIdx.x & 255);
@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(NT) step_gather_kernel(const StepArgs<T, T> a,
     using K = StepKernel<T, TZ, RY, NT, PREV, STREAM, T>;
     __shared__ T lds[2][K::SY * K::SZ];
     K k(a);
-    k.run(blockIdx.x - ngb, lds);
+    k.run(blockIdx.x, lds);
 }
 
 // H v for one FP64 vector in one launch: the first ngather workgroups gather
@@ -186,7 +186,7 @@ static int launch_typed(const StepArgs<T, TI> &a, bool prev, bool strm, hipStrea
             const dim3 grid(a.nblocks + gp->ngb), blk(NT);
 #define SPARC_SG(P, S)                                                                                           \
     hipLaunchKernelGGL((step_gather_kernel<T, TZ, RY, NT, P, S>), grid, blk, 0, stream, a, gp->g, gp->natoms, \
-                       gp->ncb, gp->nitems, gp->ngb)
+                       gp->ncb, gp->nitems)
             if (prev && strm)
                 SPARC_SG(true, true);
             else if (prev)
@@ -266,7 +266,7 @@ static int launch_step_t(const sparc_op *op, const void *yk, int64_t ldk, const 
         gp.ncb = (ns + 15) / 16;
         gp.nitems = op->natoms * gp.ncb * kGatherSplit;
         const int per = kShapes[L.shape].nt / 256;
-        gp.ngb = ((gp.nitems + per - 1) / per + 7) / 8 * 8;
+        gp.ngb = (gp.nitems + per - 1) / per;
         if ((long long)a.nblocks + gp.ngb > 0x7fffffffLL) return fail(SPARC_E_SHAPE, "too many workgroups for one launch");
     }
     ProfScope prof(prev ? 0 : 3, stream);
