@@ -226,3 +226,53 @@ def test_rayleigh_ritz_matches_dense_projection():
     Qo, _ = np.linalg.qr(Y.T)
     ref = np.linalg.eigvalsh(Qo.T @ H @ Qo)
     assert np.allclose(theta, ref, atol=1e-9 * np.abs(ref).max())
+
+
+# ----------------------------------------------------------------------------- filter bounds
+
+# Ascending Ritz values with distinct gaps, so that an off-by-one in the cutoff
+# index or a wrong shift gives a different number.
+_THETA = np.array([-3.0, -2.5, -1.0, 0.0, 0.5, 1.25, 2.0, 2.75, 3.5, 10.0])
+
+
+def test_select_bounds_exact_values():
+    """Alg. 2 takes lambda_1, the cutoff lambda_c and lambda_Nd; the reading
+    fixes lambda_1 := theta_1, lambda_c := theta_8 + 0.1 Ha (the 0.1 Ha margin
+    of Sec. 4) and lambda_Nd := 1.01 theta_max.  Exact expected values:"""
+    a0, a, b = oracle.select_bounds(_THETA, 8)
+    assert (a0, a, b) == (-3.0, 2.75 + 0.1, 1.01 * 10.0)
+    # the 8th value, not the 7th or 9th
+    assert a != 2.0 + 0.1 and a != 3.5 + 0.1
+    # input order does not matter
+    perm = np.random.default_rng(3).permutation(len(_THETA))
+    assert oracle.select_bounds(_THETA[perm], 8) == (a0, a, b)
+    # other cutoff indices and shifts
+    assert oracle.select_bounds(_THETA, 1, shift=0.25) == (-3.0, -3.0 + 0.25, 10.1)
+    assert oracle.select_bounds(_THETA, 3, shift=0.5, bfactor=1.5) == (-3.0, -1.0 + 0.5, 15.0)
+
+
+def test_select_bounds_upper_clamp_and_short_runs():
+    # b is lowered to a guaranteed upper bound only when that is smaller
+    assert oracle.select_bounds(_THETA, 8, ubound=9.0)[2] == 9.0
+    assert oracle.select_bounds(_THETA, 8, ubound=11.0)[2] == 1.01 * 10.0
+    assert oracle.select_bounds(_THETA, 8, ubound=10.1)[2] == 1.01 * 10.0
+    # fewer Ritz values than wanted states: the cutoff sits above the largest
+    th = np.array([-1.0, 4.0, 20.0])
+    assert oracle.select_bounds(th, 8) == (-1.0, 20.0 + 0.1, 1.01 * 20.0)
+    # bounds that do not satisfy a0 < a < b are refused
+    with pytest.raises(ValueError):
+        oracle.select_bounds(np.array([-1.0, 4.0, 5.0]), 8)      # a = 5.1 > b = 5.05
+    with pytest.raises(ValueError):
+        oracle.select_bounds(_THETA, 8, ubound=2.0)              # b below the cutoff
+
+
+def test_select_bounds_on_exact_spectrum():
+    """With the exact spectrum of a dense H as the Ritz values, the bounds
+    bracket the spectrum as Alg. 2 needs: a0 is lambda_1 itself, the cutoff
+    lies 0.1 Ha above lambda_8, and b is at least lambda_max."""
+    cl = _tiny_cluster(lmax=2)
+    lam = np.linalg.eigvalsh(oracle.dense_hamiltonian(cl))
+    a0, a, b = oracle.select_bounds(lam, 8, ubound=oracle.upper_bound(cl))
+    assert a0 == lam[0]
+    assert a == lam[7] + 0.1
+    assert np.sum(lam < a) >= 8 and lam[-1] <= b
