@@ -340,6 +340,12 @@ int sparc_filter_poll(sparc_server *srv, uint64_t ticket, sparc_job_result *resu
  * and the reserved device bytes. */
 int sparc_server_stats(sparc_server *srv, int64_t *done, int64_t *pending, int64_t *running, uint64_t *hbm_used);
 
+/* Cluster records the server holds on the host (clusters submitted and not
+ * yet released or failed, with their copies of V_eff and the projectors), and
+ * the number of retired ids: a released or failed cluster's record is freed
+ * once no queued request refers to it, and its id is refused from then on. */
+int sparc_server_clusters(sparc_server *srv, int64_t *records, int64_t *retired);
+
 /* Finish running requests, drop pending ones, free every cluster, stop the workers. */
 int sparc_server_destroy(sparc_server *srv);
 
@@ -354,6 +360,13 @@ uint64_t sparc_cluster_footprint(const sparc_cluster_desc *desc, int32_t lanczos
 
 const char *sparc_status_str(int status);
 const char *sparc_last_error(void);
+
+/* Number of times a library call (rocsolver_dsygvd) returned success but left
+ * the thread's HIP error state set to hipErrorStreamCaptureUnsupported, which
+ * the library then cleared (each occurrence up to the eighth is also written
+ * to stderr).  Any other error code left behind fails the call with
+ * SPARC_E_HIP instead.  Host only. */
+int64_t sparc_cleared_hip_errors(void);
 
 /* Per-kernel timing with HIP events recorded around each launch on the
  * launching stream.  kernel: 0 = fused stencil/potential/recurrence step

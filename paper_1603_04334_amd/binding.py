@@ -102,6 +102,7 @@ _SIGS = {
     "sparc_rayleigh_ritz": (_i32, [_vp, _i32, _vp, _i64, _i32, _dp, _vp, _vp, _sz, _vp]),
     "sparc_rotate": (_i32, [_i32, _vp, _i64, _i64, _i32, _vp, _vp, _i64, _vp, _sz, _vp]),
     "sparc_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "sparc_cleared_hip_errors": (_i64, []),
     "sparc_last_error": (ctypes.c_char_p, []),
     "sparc_profile_enable": (_i32, [_i32]),
     "sparc_profile_read": (_i32, [_i32, ctypes.POINTER(_i64), _dp]),
@@ -116,6 +117,7 @@ _SIGS = {
     "sparc_server_stats": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64),
                                   ctypes.POINTER(ctypes.c_uint64)]),
     "sparc_server_destroy": (_i32, [_vp]),
+    "sparc_server_clusters": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "sparc_clock": (ctypes.c_double, []),
     "sparc_cluster_footprint": (ctypes.c_uint64, [ctypes.POINTER(sparc_cluster_desc), _i32]),
     "sparc_batch_create": (_i32, [ctypes.POINTER(sparc_batch_job), _i32, _i32, ctypes.POINTER(_vp)]),
@@ -475,6 +477,12 @@ class Server:
         d, p, r, u = _i64(), _i64(), _i64(), ctypes.c_uint64()
         check(lib().sparc_server_stats(self.handle, ctypes.byref(d), ctypes.byref(p), ctypes.byref(r), ctypes.byref(u)))
         return {"done": d.value, "pending": p.value, "running": r.value, "hbm_used": u.value}
+
+    def clusters(self):
+        """(host cluster records held, retired cluster ids)."""
+        n, r = _i64(), _i64()
+        check(lib().sparc_server_clusters(self.handle, ctypes.byref(n), ctypes.byref(r)))
+        return n.value, r.value
 
     def close(self):
         if getattr(self, "handle", None):

@@ -21,10 +21,11 @@ HIP_FLAGS = [
 
 
 def sources():
-    return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    # the per-type step units take longest: start them first
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip")), key=lambda f: (not os.path.basename(f).startswith("step_"), f))
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
+def build(verbose: bool = False, jobs: int = 16) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     procs = []

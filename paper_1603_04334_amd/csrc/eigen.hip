@@ -211,7 +211,8 @@ __global__ void __launch_bounds__(kEigThreads) small_sygv_kernel(const double *_
     const int bk = has_blk ? tid / half : 0, bl = has_blk ? tid % half : 0;
     const int z0 = 2 * bk, z1 = 2 * bk + 1;
     int cur = 0;
-    for (int sweep = 0; sweep < max_sweeps && n > 1; ++sweep) {
+    bool converged = n == 1;
+    for (int sweep = 0; sweep <= max_sweeps && n > 1; ++sweep) {
         const double(*A)[kEigMax + 1] = CB[cur];
         double off = 0.0, tot = 0.0;
         for (int e = tid; e < n * n; e += nt) {
@@ -222,7 +223,12 @@ __global__ void __launch_bounds__(kEigThreads) small_sygv_kernel(const double *_
         }
         off = block_sum_eig(off, red);
         tot = block_sum_eig(tot, red);
-        if (!(off > 1e-30 * tot)) break;
+        if (!(off > 1e-30 * tot)) {
+            converged = true;
+            break;
+        }
+        // the test above also runs after the last sweep
+        if (sweep == max_sweeps) break;
         for (int r = 0; r < np - 1; ++r) {
             const double(*S)[kEigMax + 1] = CB[cur];
             double(*D)[kEigMax + 1] = CB[cur ^ 1];
@@ -281,7 +287,8 @@ __global__ void __launch_bounds__(kEigThreads) small_sygv_kernel(const double *_
         const int k = e % n, c = e / n;
         evec[(long long)rank[c] * n + k] = Q[k][c];
     }
-    if (tid == 0) info[0] = 0;
+    // n + 1: the off-diagonal mass was still above the tolerance after max_sweeps
+    if (tid == 0) info[0] = converged ? 0 : n + 1;
 }
 
 int launch_small_sygv(const double *Hs, const double *Ms, int n, double *theta, double *evec, int *info,

@@ -27,6 +27,7 @@
 #include <new>
 #include <thread>
 #include <unordered_map>
+#include <unordered_set>
 
 #include "internal.hpp"
 
@@ -88,6 +89,7 @@ struct sparc_server {
     bool stop = false;
     std::deque<Request> pending;
     std::unordered_map<uint64_t, Cluster *> clusters;
+    std::unordered_set<uint64_t> retired;  // ids of released or failed clusters (their records are freed)
     std::map<uint64_t, sparc_job_result> done;
     std::map<uint64_t, int> open;  // tickets submitted and not yet polled as done
     uint64_t next_ticket = 1;
@@ -314,6 +316,13 @@ void worker_main(sparc_server *srv)
                 ++p;
             }
         }
+        if (c.released) {
+            // no request refers to it any more: drop the record with its host
+            // copies of V_eff and the projectors; the id stays refused
+            srv->clusters.erase(r.cluster);
+            srv->retired.insert(r.cluster);
+            delete &c;
+        }
         lk.unlock();
         srv->cv.notify_all();
     }
@@ -396,6 +405,7 @@ int sparc_filter_submit(sparc_server *srv, const sparc_filter_job *job, uint64_t
         if (c.footprint > srv->budget) return fail(SPARC_E_NOMEM, "cluster footprint exceeds the device budget");
     }
     std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->retired.count(job->cluster)) return fail(SPARC_E_JOB, "cluster already released or failed");
     auto ci = srv->clusters.find(job->cluster);
     Cluster *c = ci == srv->clusters.end() ? nullptr : ci->second;
     if (fresh) {
@@ -437,6 +447,15 @@ int sparc_server_stats(sparc_server *srv, int64_t *done, int64_t *pending, int64
     if (pending) *pending = (int64_t)srv->pending.size();
     if (running) *running = srv->n_running;
     if (hbm_used) *hbm_used = srv->used;
+    return SPARC_OK;
+}
+
+int sparc_server_clusters(sparc_server *srv, int64_t *records, int64_t *retired)
+{
+    if (!srv) return fail(SPARC_E_ARG, "null server");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (records) *records = (int64_t)srv->clusters.size();
+    if (retired) *retired = (int64_t)srv->retired.size();
     return SPARC_OK;
 }
 

@@ -221,9 +221,12 @@ def test_serve_admission_budget():
             assert time.time() < deadline, "requests did not finish"
             time.sleep(0.0005)
         st = srv.stats()
+        recs = srv.clusters()
     finally:
         srv.close()
     assert peak <= budget
+    # every session ended with a release: no host record of a cluster remains
+    assert recs == (0, len(ids))
     assert st["hbm_used"] == 0 and st["pending"] == 0 and st["running"] == 0
     res = {tickets[t]: r for t, r in out.items()}
     assert all(r["status"] == 0 for r in res.values())
@@ -285,6 +288,9 @@ def test_serve_errors_and_failure_isolation():
             srv.poll(tg0)  # retired
         assert e.value.status == SPARC_E_TICKET
         assert srv.stats()["hbm_used"] == 0
+        # both clusters are finished (one released, one failed): their host
+        # records are gone and only their ids are kept
+        assert srv.clusters() == (0, 2)
     finally:
         srv.close()
     # the good cluster's results equal those of a run without the failing one
