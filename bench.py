@@ -1,15 +1,16 @@
 """Benchmark of the Chebyshev-filter hot path on one MI355X.
 
-Workload: the medium synthetic cluster (96^3 grid, h = 0.4 bohr, 16 atoms with
-4 Kleinman-Bylander projectors each, 64 orbitals N(0,1), degree m = 24,
-stencil order 12).  One step is one filtered-subspace pass over the resident
-orbital block: 40-step FP64 Lanczos bounds on the device, the Chebyshev filter
-in the selected dtype, FP64 Rayleigh-Ritz on the device and the subspace
-rotation; each pass starts from the orbitals the previous one rotated.  ``value`` is filtered orbital*gridpoint updates per second of the
-whole step (N_d * N_s * m / step time).
+Workload (default): the largest single-GPU cluster, a 160^3 grid with h = 0.35
+bohr, 128 atoms with 9 Kleinman-Bylander projectors each (l = 0, 1, 2), 600
+orbitals N(0,1), filter degree m = 30, stencil order 12.  One step is one
+filtered-subspace pass over the resident orbital block: 40-step FP64 Lanczos
+bounds on the device, the Chebyshev filter in the selected dtype (FP32 by
+default, FP32 accumulation), FP64 Rayleigh-Ritz on the device and the
+subspace rotation; each pass starts from the orbitals the previous one
+rotated.  ``value`` is filtered orbital*gridpoint updates per second of the
+whole step (N_d * N_s * m / step time).  The FP64 pass is measured beside it.
 
-Prints ONE JSON line (rank 0).  Defaults: 1 GPU, 10 timed steps, 3 warmup.
-Modes: --dtype f32 (default; FP64 also measured and reported beside it) or f64.
+Prints ONE JSON line.  Defaults: 1 GPU, 5 timed steps, 1 warmup.
 """
 from __future__ import annotations
 
@@ -27,18 +28,21 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 KSTEPS_LANCZOS = 40
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic_cluster96.txt")
-STENCIL_SRCS = [os.path.join(ROOT, "paper_1603_04334_amd", "csrc", f) for f in ("stencil.hip", "step_kernel.hpp")]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic_cluster160.txt")
+STENCIL_SRCS = [os.path.join(ROOT, "paper_1603_04334_amd", "csrc", f)
+                for f in ("fstep.hip", "fstep_kernel.hpp", "fstep_launch.hpp", "nonlocal_kernel.hpp")]
 
 
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=10)
-    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--dtype", choices=["f32", "f64"], default="f32")
+    p.add_argument("--workload", choices=["large", "medium", "small"], default="large")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-fp64-compare", action="store_true")
+    p.add_argument("--no-secondary", action="store_true", help="skip the medium-cluster and small-cluster lines")
     p.add_argument("--no-batch", action="store_true", help="skip the batched uneven-cluster measurement")
     p.add_argument("--batch-only", action="store_true", help="print only the batched measurement")
     p.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
@@ -48,12 +52,14 @@ def parse():
     p.add_argument("--serve-requests", type=int, default=500, help="requests per rate point (5 per cluster)")
     p.add_argument("--serve-workers", type=int, default=4)
     p.add_argument("--copy-calibration", action="store_true",
-                   help="run only a plain device copy of known size (for counter calibration)")
+                   help="run only the library's reference copy kernel on 4 GiB (counter calibration)")
+    p.add_argument("--filter-only", action="store_true",
+                   help="run only the filter of the workload (warmup + steps launches; for counter runs)")
     return p.parse_args()
 
 
 def source_hash() -> str:
-    """Hash of the step kernel's sources (launch code and kernel body)."""
+    """Hash of the dominant launch's sources (vector step and gather)."""
     h = hashlib.sha256()
     for f in STENCIL_SRCS:
         h.update(open(f, "rb").read())
@@ -61,8 +67,8 @@ def source_hash() -> str:
 
 
 def read_traffic(dtype):
-    """HBM bytes per recurrence-step launch from committed counter runs, or
-    None when absent or taken on a different kernel source."""
+    """Calibrated HBM bytes per recurrence-step launch from committed counter
+    runs, or None when absent or taken on a different kernel source."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -78,52 +84,89 @@ def read_traffic(dtype):
         return None
 
 
-def copy_calibration():
+def copy_bandwidth(nbytes=4 << 30, reps=10):
+    """GB/s (read + written) of the library's reference copy kernel."""
     import torch
-    n = 1 << 28  # 256 Mi floats = 1 GiB read + 1 GiB written
-    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    from paper_1603_04334_amd import binding
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    for _ in range(5):
-        b.copy_(a)
+    binding.stream_copy(b, a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 5}))
+    e0.record()
+    for _ in range(reps):
+        binding.stream_copy(b, a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def alg_bytes_per_step_launch(case, cl, s):
+    """Algorithmic HBM bytes of one recurrence-step launch (the fused step with
+    Y_{k-1} and the projector gather of the same Y_k): read Y_k and Y_{k-1},
+    write Y_{k+1} (s bytes per orbital*gridpoint each), read V_eff once (s per
+    gridpoint), read the projector values once (s per cube point and
+    projector) and write the gather's 8 split partials (s per projector and
+    orbital each).  The gather's second read of Y_k at the cube points is
+    an implementation cost and is not counted."""
+    chi = sum(int(np.prod(a.ext)) * a.nproj for a in cl.atoms)
+    return 3 * s * cl.nd * case.ns + s * cl.nd + s * chi + s * 8 * cl.nproj_total * case.ns
 
 
 class Pass:
     """Resident state of one workload and one dtype."""
 
-    def __init__(self, case, cluster, dtype):
+    def __init__(self, case, cluster, op, dtype, tune=True):
         import torch
         from paper_1603_04334_amd import binding, inputs
         self.binding = binding
         self.case = case
         self.cl = cluster
+        self.op = op
         self.dt = torch.float32 if dtype == "f32" else torch.float64
         self.code = binding.SPARC_F32 if dtype == "f32" else binding.SPARC_F64
-        self.op = binding.Operator(cluster)
-        X = inputs.orbitals(cluster.nd, case.ns, case.seed)
-        self.X = torch.from_numpy(X).to(self.dt).cuda()
-        del X
+        self.tuned = op.autotune(self.code, case.ns) if tune else None
+        self.X = inputs.device_orbitals(cluster.nd, case.ns, case.seed, self.dt)
         self.Y = torch.empty_like(self.X)
         self.R = torch.empty_like(self.X)
         self.v0 = torch.from_numpy(inputs.lanczos_start(cluster.nd, case.seed)).cuda()
-        self.ws = self.op.workspace(self.code, case.ns, 1)
-        self.ub = self.op.upper_bound()
+        self.ws = op.workspace(self.code, case.ns, 1)
+        self.ub = op.upper_bound()
         self.bounds = None
         self.ritz = None
+        self.first_ritz = None
+        self.stage_ms = None
 
-    def step(self, profile_filter=False):
+    def step(self, profile_filter=False, stages=False):
+        import torch
         b = self.binding
+        t = [time.perf_counter()]
         _, _, theta = self.op.lanczos(KSTEPS_LANCZOS, self.v0)
         a0, a, bb = b.select_bounds(theta, 8, ubound=self.ub)
         self.bounds = (a0, a, bb)
+        t.append(time.perf_counter())
         if profile_filter:
             b.profile.enable(True)
         self.op.cheb_filter(self.X, self.case.m, a0, a, bb, Y=self.Y, ws=self.ws)
         if profile_filter:
             b.profile.enable(False)
+        if stages:
+            torch.cuda.synchronize()
+        t.append(time.perf_counter())
         self.ritz, Qt = self.op.rayleigh_ritz(self.Y)
+        if self.first_ritz is None:
+            self.first_ritz = self.ritz.copy()
+        t.append(time.perf_counter())
         b.rotate(self.Y, Qt, out=self.R)
+        if stages:
+            torch.cuda.synchronize()
+        t.append(time.perf_counter())
+        if stages:
+            self.stage_ms = {k: (t[i + 1] - t[i]) * 1e3 for i, k in enumerate(("lanczos", "filter", "rayleigh_ritz",
+                                                                                 "rotation"))}
         # the next pass continues from the rotated orbitals, as the SCF passes do
         self.X, self.R = self.R, self.X
 
@@ -144,19 +187,33 @@ def timed(fn, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
-def alg_bytes_per_step_launch(case, cl, s):
-    """Algorithmic HBM bytes of one recurrence-step launch, which runs the
-    fused step and the projector gather of the same Y_k: read Y_k and Y_{k-1},
-    write Y_{k+1} (s bytes per orbital*gridpoint each), read V_eff once (s
-    bytes per gridpoint); the gather reads Y_k at the cube points again (s per
-    orbital*cube point), chi once per group of 16 orbitals (s per cube point
-    and projector) and writes its 8 split partials (s per projector and
-    orbital each)."""
-    cube = sum(int(np.prod(a.ext)) for a in cl.atoms)
-    chi = sum(int(np.prod(a.ext)) * a.nproj for a in cl.atoms)
-    ncb = (case.ns + 15) // 16
-    gather = s * (case.ns * cube + ncb * chi + 8 * cl.nproj_total * case.ns)
-    return 3 * s * cl.nd * case.ns + s * cl.nd + gather
+def measure_pass(case, cl, op, dtype, steps, warmup, kernel_stats=False):
+    """Whole-step and filter-only timing of one dtype; kernel statistics of the
+    recurrence-step launches (HIP events on the launching stream) and a stage
+    breakdown when asked."""
+    import torch
+    from paper_1603_04334_amd import binding
+    p = Pass(case, cl, op, dtype)
+    out = {}
+    t_step = timed(p.step, steps, warmup)
+    out["ms_per_step"] = t_step * 1e3
+    out["first_ritz"] = p.first_ritz
+    out["bounds"] = p.bounds
+    out["tuned"] = p.tuned
+    if kernel_stats:
+        binding.profile.reset()
+        torch.cuda.synchronize()
+        for _ in range(steps):
+            p.step(profile_filter=True)
+        torch.cuda.synchronize()
+        out["kernels"] = {k: binding.profile.read(k) for k in range(4)}
+        binding.profile.reset()
+        p.step(stages=True)
+        out["stages_ms"] = p.stage_ms
+    out["filter_ms"] = timed(p.filter_only, steps, 1) * 1e3
+    del p
+    torch.cuda.empty_cache()
+    return out
 
 
 def batch_measure(reps=5, nclusters=64):
@@ -168,16 +225,13 @@ def batch_measure(reps=5, nclusters=64):
     import torch
     from paper_1603_04334_amd import binding, inputs
     recipe = inputs.batch_recipe(nclusters=nclusters)
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(4)
     jobs32, jobs64, ops, work = [], [], [], 0
     for r in recipe:
         cl = inputs.make_cluster(r["n"], r["h"], r["natoms"], r["zmax"], r["lmax"], r["seed"])
         op = binding.Operator(cl)
         _, _, theta = op.lanczos(KSTEPS_LANCZOS, torch.from_numpy(inputs.lanczos_start(cl.nd, r["seed"])).cuda())
         a0, a, b = binding.select_bounds(theta, 8, ubound=op.upper_bound())
-        op.autotune(binding.SPARC_F32, r["ns"])
-        X = torch.randn((r["ns"], cl.nd), generator=gen, device="cuda", dtype=torch.float32)
+        X = inputs.device_orbitals(cl.nd, r["ns"], r["seed"])
         jobs32.append((op, X, torch.empty_like(X), r["m"], a0, a, b))
         X64 = X.double()
         jobs64.append((op, X64, torch.empty_like(X64), r["m"], a0, a, b))
@@ -227,11 +281,9 @@ class ServeSetup:
         specs = self.specs
         maxnd = max(c["n"] ** 3 for c in specs.values())
         maxns = max(c["ns"] for c in specs.values())
-        gen = torch.Generator(device="cuda")
-        gen.manual_seed(5)
-        self.X64 = torch.randn(maxnd * maxns, generator=gen, device="cuda", dtype=torch.float64)
+        self.X64 = inputs.device_orbitals(maxnd * maxns, 1, 5, torch.float64).view(-1)
         self.X32 = self.X64.float() if any(c["fp32"] for c in specs.values()) else None
-        self.v0 = torch.randn(maxnd, generator=gen, device="cuda", dtype=torch.float64)
+        self.v0 = inputs.device_orbitals(maxnd, 1, 6, torch.float64).view(-1)
         torch.cuda.synchronize()
         self.descs = {}
         for sd, c in specs.items():
@@ -252,7 +304,6 @@ def serve_point(setup, rate, nclusters, workers):
     srv = binding.Server(workers=workers, budget=int(SERVE_BUDGET), lanczos_steps=KSTEPS_LANCZOS)
     done = []          # (session index, pass, result)
     open_t = {}        # ticket -> (session index, pass)
-    failed_sessions = {}
     lag = 0.0
     nxt = 0
     try:
@@ -272,25 +323,22 @@ def serve_point(setup, rate, nclusters, workers):
                     continue
                 i, k = open_t.pop(tk)
                 done.append((i, k, r))
-                if r["status"] != 0:
-                    failed_sessions[i] = r["status"]
-                elif k + 1 < SERVE_STEPS:
+                if r["status"] == 0 and k + 1 < SERVE_STEPS:
                     c = sessions[i]["cluster"]
                     open_t[srv.submit(c["seed"], release=k + 2 == SERVE_STEPS)] = (i, k + 1)
             if time.time() > deadline:
                 raise RuntimeError("serving run did not finish")
             wait = (t0 + sessions[nxt]["t_arrive"] - binding.clock()) if nxt < len(sessions) else 1e-3
             time.sleep(min(max(wait, 0.0), 5e-4))
+        records = srv.clusters()
     finally:
         srv.close()
     ok = [(i, k, r) for i, k, r in done if r["status"] == 0]
     failed = {}
-    for i, k, r in done:
-        if r["status"] != 0:
-            failed[binding.status_name(r["status"])] = failed.get(binding.status_name(r["status"]), 0) + 1
     failures = []
     for i, k, r in done:
         if r["status"] != 0:
+            failed[binding.status_name(r["status"])] = failed.get(binding.status_name(r["status"]), 0) + 1
             c = sessions[i]["cluster"]
             failures.append({"n": c["n"], "ns": c["ns"], "m": c["m"], "natoms": c["natoms"], "fp32": c["fp32"],
                              "seed": c["seed"], "pass": k, "status": binding.status_name(r["status"]),
@@ -312,11 +360,12 @@ def serve_point(setup, rate, nclusters, workers):
             "p50_ms_f64": q(lat[~is32], 50), "p99_ms_f64": q(lat[~is32], 99),
             "session_p50_ms": q(sess, 50), "session_p99_ms": q(sess, 99),
             "throughput_req_s": len(ok) / span, "updates_per_s": upd / span, "span_s": span,
-            "max_arrival_lag_ms": lag * 1e3}
+            "max_arrival_lag_ms": lag * 1e3, "host_cluster_records_left": records[0]}
 
 
 def serve_measure(rates, nrequests, workers):
     import torch
+    from paper_1603_04334_amd import binding
     nclusters = max(1, nrequests // SERVE_STEPS)
     setup = ServeSetup(nclusters)
     # warm-up: kernels, library handles, allocator pools
@@ -328,30 +377,78 @@ def serve_measure(rates, nrequests, workers):
     out = {"workload": f"{nclusters} cluster sessions x {SERVE_STEPS} filtered-subspace passes (Lanczos bounds on "
                        f"the first), grid edge log-uniform 24-128, h=0.45, 1-64 atoms, N_s = N_e/2+30, degree 20-30, "
                        f"FP32:FP64 = 80:20, Poisson session arrivals at rate/{SERVE_STEPS}, passes chained",
-           "workers": workers, "budget_bytes": SERVE_BUDGET, "points": points}
+           "workers": workers, "budget_bytes": SERVE_BUDGET, "points": points,
+           "cleared_hip_errors": int(binding.lib().sparc_cleared_hip_errors())}
     del setup
     torch.cuda.empty_cache()
     return out
 
 
-def cpu_baseline(case, cl):
-    """The C oracle's FP64 filter on the host, in groups of 8 orbitals of the
-    same cluster until about 10 s of work (or all orbitals) are done."""
+def secondary(args):
+    """Filter throughput of the medium cluster (96^3, 64 orbitals, m = 24) in
+    FP32 and FP64 and the latency of one whole pass and of one filter on the
+    small cluster (24^3, 8 orbitals, m = 20), which is latency-bound."""
+    import torch
+    from paper_1603_04334_amd import binding, inputs
+    out = {}
+    c = inputs.MEDIUM
+    cl = inputs.case_cluster(c.name)
+    op = binding.Operator(cl)
+    med = {"workload": c.name}
+    for dt in ("f32", "f64"):
+        p = Pass(c, cl, op, dt)
+        p.step()
+        ms = timed(p.filter_only, 20, 2) * 1e3
+        med[f"filter_{dt}"] = {"ms": ms, "value": cl.nd * c.ns * c.m / (ms * 1e-3)}
+        del p
+    out["medium"] = med
+    c = inputs.SMALL
+    cl = inputs.case_cluster(c.name)
+    op = binding.Operator(cl)
+    p = Pass(c, cl, op, "f64", tune=False)
+    p.step()
+    step_ms = timed(p.step, 20, 3) * 1e3
+    filt_ms = timed(p.filter_only, 50, 3) * 1e3
+    out["small_latency"] = {"workload": c.name, "pass_ms": step_ms, "filter_ms": filt_ms,
+                            "pass": "lanczos40_fp64+cheb_filter_fp64+rayleigh_ritz_fp64+rotation"}
+    del p
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(case, cl, op, bounds, ncols=16):
+    """The C oracle's FP64 filter on the host's OpenMP threads, on a seeded
+    subset of the workload's orbitals (the first ncols columns of the same
+    device-drawn block), with the bounds the GPU passes used; the metric is
+    per orbital*gridpoint, so the subset's rate is the rate of the whole
+    block.  The same columns are filtered on the GPU in FP64 and FP32 and
+    compared with the oracle (per-orbital relative error)."""
+    import torch
     import oracle
     from paper_1603_04334_amd import inputs
-    a0, a, b = -2.0, 3.0, oracle.upper_bound(cl)
-    done, dt = 0, 0.0
-    while done < case.ns and dt < 10.0:
-        cols = list(range(done, min(case.ns, done + 8)))
-        X = inputs.orbitals(cl.nd, case.ns, case.seed, cols=cols)
-        t0 = time.perf_counter()
-        oracle.cheb_filter(cl, X, case.m, a0, a, b)
-        dt += time.perf_counter() - t0
-        done += len(cols)
-    return {"value": done * cl.nd * case.m / dt, "unit": "orbital*gridpts/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"FP64 C oracle Chebyshev filter (degree {case.m}) of {done} of the {case.ns} "
-                      f"orbitals of the same cluster, {dt:.1f} s on the host"}
+    a0, a, b = bounds
+    X32 = inputs.device_orbitals(cl.nd, case.ns, case.seed)[:ncols].contiguous()
+    Xh = X32.double().cpu().numpy()
+    t0 = time.perf_counter()
+    ref = oracle.cheb_filter(cl, Xh, case.m, a0, a, b)
+    dt = time.perf_counter() - t0
+    out = {"value": ncols * cl.nd * case.m / dt, "unit": "orbital*gridpts/s", "cores": oracle.num_threads(),
+           "kind": "oracle",
+           "sample": f"FP64 C oracle Chebyshev filter (degree {case.m}) of {ncols} of the {case.ns} orbitals of "
+                     f"the same cluster and bounds, {dt:.1f} s on the host; the rate of the whole block is "
+                     f"extrapolated from this subset (columns are independent)"}
+
+    def rel(g, r):
+        return float((np.linalg.norm(g - r, axis=1) / np.linalg.norm(r, axis=1)).max())
+
+    y64 = op.cheb_filter(X32.double(), case.m, a0, a, b).cpu().numpy()
+    n32 = min(4, ncols)
+    ref32 = oracle.cheb_filter(inputs.round_cluster_f32(cl), Xh[:n32], case.m, a0, a, b)
+    y32 = op.cheb_filter(X32[:n32].contiguous(), case.m, a0, a, b).double().cpu().numpy()
+    out["parity"] = {"columns_f64": ncols, "columns_f32": n32, "max_rel_err_f64": rel(y64, ref),
+                     "max_rel_err_f32": rel(y32, ref32), "tolerance_f64": 1e-12, "tolerance_f32": 5e-5}
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -361,11 +458,17 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
-    if args.copy_calibration:
-        copy_calibration()
-        return
     from paper_1603_04334_amd import binding, inputs
     binding.lib()
+    if args.copy_calibration:
+        n = 4 << 30
+        a = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        bb = torch.empty_like(a)
+        for _ in range(5):
+            binding.stream_copy(bb, a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 5}))
+        return
     if args.batch_only:
         print(json.dumps(batch_measure()), flush=True)
         return
@@ -373,30 +476,30 @@ def main():
     if args.serve_only:
         print(json.dumps(serve_measure(rates, args.serve_requests, args.serve_workers)), flush=True)
         return
-    case = inputs.MEDIUM
+    case = {"large": inputs.LARGE, "medium": inputs.MEDIUM, "small": inputs.SMALL}[args.workload]
     cl = inputs.case_cluster(case.name)
+    op = binding.Operator(cl)
+    if args.filter_only:
+        p = Pass(case, cl, op, args.dtype)
+        p.step()
+        for _ in range(args.warmup + args.steps):
+            p.filter_only()
+        torch.cuda.synchronize()
+        print(json.dumps({"filter_only_runs": args.warmup + args.steps, "workload": case.name, "dtype": args.dtype}))
+        return
     s = 4 if args.dtype == "f32" else 8
-
-    main_pass = Pass(case, cl, args.dtype)
-    # timed region: K whole steps
-    t_step = timed(main_pass.step, args.steps, args.warmup)
     updates = cl.nd * case.ns * case.m
-    # kernel timing: the same steps again with per-launch events on the filter's kernels
-    binding.profile.reset()
-    torch.cuda.synchronize()
-    for _ in range(args.steps):
-        main_pass.step(profile_filter=True)
-    torch.cuda.synchronize()
-    n_launch, ms = binding.profile.read(0)
-    n_g, ms_g = binding.profile.read(1)
-    n_sc, ms_sc = binding.profile.read(2)
-    n_f, ms_f = binding.profile.read(3)
-    binding.profile.reset()
+    print(f"bench: {case.name} {args.dtype}: timing {args.steps} steps", file=sys.stderr, flush=True)
+    main_res = measure_pass(case, cl, op, args.dtype, args.steps, args.warmup, kernel_stats=True)
+    t_step = main_res["ms_per_step"] * 1e-3
+    n_launch, ms = main_res["kernels"][0]
+    n_sc, ms_sc = main_res["kernels"][2]
+    n_f, ms_f = main_res["kernels"][3]
     avg_s = ms / 1e3 / max(n_launch, 1)
     alg = alg_bytes_per_step_launch(case, cl, s)
     achieved = alg / avg_s / 1e9
-    traffic = read_traffic(args.dtype)
-    t_filter = timed(main_pass.filter_only, args.steps, 1)
+    copy_gbs = copy_bandwidth()
+    tz, ty, cx, cg = op.step_config(binding.SPARC_F32 if args.dtype == "f32" else binding.SPARC_F64, case.ns)
 
     out = {
         "metric": "filtered orbital*gridpts/s",
@@ -414,37 +517,45 @@ def main():
         "config": {"workload": case.name, "grid": [case.n] * 3, "h": case.h, "atoms": case.natoms,
                    "projectors_per_atom": (case.lmax + 1) ** 2, "orbitals": case.ns, "degree": case.m,
                    "stencil_radius": 6, "step": "lanczos40_fp64+cheb_filter+rayleigh_ritz_fp64+rotation",
-                   "parallelism": "single_gpu"},
-        "filter_only": {"value": updates / t_filter, "ms": t_filter * 1e3},
+                   "parallelism": "single_gpu", "tile": {"z": tz, "y": ty, "chunk_x": cx, "col_group": cg}},
+        "filter_only": {"value": updates / (main_res["filter_ms"] * 1e-3), "ms": main_res["filter_ms"]},
+        "stages_ms": main_res["stages_ms"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "step_gather_kernel (fused stencil + local potential + recurrence with Y_{k-1}, and the projector gather of Y_k)",
-                     "launches": n_launch, "avg_launch_us": avg_s * 1e6,
-                     "alg_bytes_per_launch": alg},
-        "gather_kernel": {"launches": n_g, "avg_launch_us": ms_g / max(n_g, 1) * 1e3},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(args.dtype),
+                     "kernel": "fstep_kernel (vector stencil + local potential + recurrence with Y_{k-1}, with the "
+                               "projector gather of Y_k in its last workgroups)",
+                     "launches": n_launch, "avg_launch_us": avg_s * 1e6, "alg_bytes_per_launch": alg,
+                     "copy_kernel_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "scatter_kernel": {"launches": n_sc, "avg_launch_us": ms_sc / max(n_sc, 1) * 1e3},
         "first_step_kernel": {"launches": n_f, "avg_launch_us": ms_f / max(n_f, 1) * 1e3},
-        "bounds": list(main_pass.bounds),
+        "bounds": list(main_res["bounds"]),
     }
-    tz, ty, cx = main_pass.op.step_config(main_pass.code, case.ns)
-    out["config"]["tile"] = {"z": tz, "y": ty, "chunk_x": cx}
     if not args.no_fp64_compare and args.dtype == "f32":
-        del main_pass
-        torch.cuda.empty_cache()
-        p64 = Pass(case, cl, "f64")
-        t64 = timed(p64.step, args.steps, args.warmup)
-        t64f = timed(p64.filter_only, args.steps, 1)
-        out["fp64"] = {"value": updates / t64, "ms_per_step": t64 * 1e3, "filter_only": updates / t64f,
-                       "filter_ms": t64f * 1e3}
-        del p64
+        print("bench: FP64 pass", file=sys.stderr, flush=True)
+        r64 = measure_pass(case, cl, op, "f64", args.steps, args.warmup)
+        out["fp64"] = {"value": updates / (r64["ms_per_step"] * 1e-3), "ms_per_step": r64["ms_per_step"],
+                       "filter_only": updates / (r64["filter_ms"] * 1e-3), "filter_ms": r64["filter_ms"]}
+        # the first pass of both runs starts from the same block with the same
+        # (FP64 Lanczos) bounds: FP32 filter + FP64 Rayleigh-Ritz against the
+        # FP64 filter + FP64 Rayleigh-Ritz
+        d = np.abs(main_res["first_ritz"] - r64["first_ritz"])
+        out["ritz_f32_vs_f64"] = {"max_abs_diff_ha": float(d.max()), "tolerance_ha": 1e-6,
+                                  "lowest": float(main_res["first_ritz"][0])}
+    if not args.no_secondary and args.workload == "large":
+        print("bench: medium and small clusters", file=sys.stderr, flush=True)
+        out.update(secondary(args))
     if not args.no_batch:
+        print("bench: batched clusters", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         out["batched"] = batch_measure()
     if not args.no_serve:
+        print("bench: serving", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         out["serving"] = serve_measure(rates, args.serve_requests, args.serve_workers)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case, cl)
+        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(case, cl, op, main_res["bounds"],
+                                           ncols=16 if args.workload == "large" else min(case.ns, 16))
     print(json.dumps(out), flush=True)
 
 

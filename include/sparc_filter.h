@@ -196,9 +196,11 @@ size_t sparc_rotate_workspace_bytes(int32_t dtype, int32_t ns);
  * Y (ldy) is an nd x ns block of the given dtype, Q an FP64 ns x ns
  * column-major device matrix (rounded to dtype for an FP32 block), ws a device
  * workspace of sparc_rotate_workspace_bytes(dtype, ns) bytes, out (ldo) an
- * nd x ns block of dtype.  Sums run in dtype.  Y, out and ws must not
- * overlap.  Asynchronous.  Errors: SPARC_E_ARG, SPARC_E_SHAPE,
- * SPARC_E_WORKSPACE, SPARC_E_ALIAS, SPARC_E_HIP. */
+ * nd x ns block of dtype.  Sums run in dtype.  Blocks of up to 64 (FP32) /
+ * 32 (FP64) columns take the library's kernel, which reads Y once; wider
+ * blocks a rocBLAS GEMM (atomics off, so results are reproducible).  Y, out
+ * and ws must not overlap.  Asynchronous.  Errors: SPARC_E_ARG,
+ * SPARC_E_SHAPE, SPARC_E_WORKSPACE, SPARC_E_ALIAS, SPARC_E_HIP. */
 int sparc_rotate(int32_t dtype, const void *Y, int64_t ldy, int64_t nd, int32_t ns, const double *Q,
                  void *out, int64_t ldo, void *ws, size_t ws_bytes, void *stream);
 
@@ -358,6 +360,14 @@ uint64_t sparc_cluster_footprint(const sparc_cluster_desc *desc, int32_t lanczos
 
 /* ------------------------------------------------------------- diagnostics */
 
+/* Plain device copy of `bytes` bytes (a multiple of 16, both addresses
+ * 16-byte aligned, not overlapping), one 16-byte unit per lane with
+ * non-temporal accesses: the reference bandwidth the step kernels are
+ * compared with, and the known-size workload that calibrates the hardware
+ * traffic counters.  Asynchronous on stream.
+ * Errors: SPARC_E_ARG, SPARC_E_ALIAS, SPARC_E_SHAPE, SPARC_E_HIP. */
+int sparc_stream_copy(void *dst, const void *src, size_t bytes, void *stream);
+
 const char *sparc_status_str(int status);
 const char *sparc_last_error(void);
 
@@ -378,32 +388,45 @@ int sparc_profile_enable(int32_t on);
 int sparc_profile_read(int32_t kernel, int64_t *launches, double *total_ms);
 int sparc_profile_reset(void);
 
-/* Override the launch configuration of the fused step kernel for one dtype:
- * tile extent along z and y (one of 32x16, 32x32, 32x48, 64x8, 64x16) and the number
- * of x-planes per workgroup (chunk_x <= 0: library choice).  tile_z = tile_y
- * = 0 restores the library's tile choice.  Applies to blocks of every width.
- * Results do not depend on the configuration.  Not thread-safe against calls
- * that use the op.
+/* Override the launch configuration of the vector step kernels (the fused
+ * stencil / potential / projector scatter / recurrence pass with the
+ * projections of its result) for one dtype: patch extent along z and y
+ * (tile_z = 32; tile_y 16, 32 or 64 for FP32, 8, 16 or 32 for FP64), the
+ * number of x-planes per workgroup (chunk_x <= 0: library choice; rounded up
+ * to a multiple of 8) and the column group (col_group <= 0: library choice;
+ * that many columns of one patch go to consecutive workgroups, so they share
+ * V_eff and the projector values in the L2 cache).  tile_z = tile_y = 0
+ * restores the library's patch choice.  Applies to blocks of every width.
+ * The x split and the column group never change results; the patch height
+ * changes the order in which projections are summed (results then agree to
+ * rounding).  Not thread-safe against calls that use the op.
  * Errors: SPARC_E_ARG (null op, bad dtype, unsupported tile). */
-int sparc_op_set_launch(sparc_op *op, int32_t dtype, int32_t tile_z, int32_t tile_y, int32_t chunk_x);
+int sparc_op_set_launch(sparc_op *op, int32_t dtype, int32_t tile_z, int32_t tile_y, int32_t chunk_x,
+                        int32_t col_group);
 
-/* Measure every tile shape and a few x-chunk lengths of the fused step kernel
- * for this op, dtype and column count on scratch blocks (allocated and freed
- * here), apply the fastest to the op for blocks of ns columns (other widths
- * keep the library's choice), and return it (out params may be NULL; best_us =
- * microseconds per recurrence step).
- * Results are cached per (grid, ns, dtype) in the process and, when the
- * environment variable SPARC_TUNE_CACHE names a file, appended to and read
- * from that file.  Synchronous.  Not thread-safe against calls using the op.
- * Errors: SPARC_E_ARG, SPARC_E_NOMEM, SPARC_E_HIP. */
+/* Measure the patch heights, a few x splits and column groups of the vector
+ * step kernels for this op (its grid, atoms and projectors), dtype and
+ * column count on scratch blocks (allocated and freed here), timing the launch
+ * a filter step makes (projections in and out), apply the fastest to the op
+ * for blocks of ns columns (other widths keep the library's choice), and
+ * return it (out params may be NULL; best_us = microseconds per recurrence
+ * step).  Results are cached per (grid, atoms, projectors, ns, dtype) in the
+ * process and, when the environment variable SPARC_TUNE_CACHE names a file,
+ * appended to and read from that file.  Synchronous.  Not thread-safe against
+ * calls using the op.
+ * Errors: SPARC_E_ARG, SPARC_E_SHAPE (the grid's z extent is not a multiple
+ * of 4 FP32 / 2 FP64 nodes, or no patch plan is usable: nothing to tune),
+ * SPARC_E_NOMEM, SPARC_E_HIP. */
 int sparc_autotune(sparc_op *op, int32_t dtype, int32_t ns, void *stream, int32_t *tile_z, int32_t *tile_y,
-                   int32_t *chunk_x, double *best_us);
+                   int32_t *chunk_x, int32_t *col_group, double *best_us);
 
-/* Launch configuration of the fused step kernel for a dtype and ns: tile
- * extent along z and y and the x-chunk length, as chosen by the library for
- * the op (out parameters may be NULL). */
+/* Launch configuration of the step kernels for a dtype and ns as chosen by
+ * the library for the op (out parameters may be NULL).  For grids the vector
+ * kernels take: tile_z = 32, tile_y, chunk_x and col_group of the vector
+ * launch; otherwise the scalar kernels' patch (32 x 16), x-chunk and
+ * col_group = 1. */
 int sparc_step_config(const sparc_op *op, int32_t dtype, int32_t ns, int32_t *tile_z, int32_t *tile_y,
-                      int32_t *chunk_x);
+                      int32_t *chunk_x, int32_t *col_group);
 
 #ifdef __cplusplus
 }

@@ -103,13 +103,14 @@ _SIGS = {
     "sparc_rotate": (_i32, [_i32, _vp, _i64, _i64, _i32, _vp, _vp, _i64, _vp, _sz, _vp]),
     "sparc_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "sparc_cleared_hip_errors": (_i64, []),
+    "sparc_stream_copy": (_i32, [_vp, _vp, _sz, _vp]),
     "sparc_last_error": (ctypes.c_char_p, []),
     "sparc_profile_enable": (_i32, [_i32]),
     "sparc_profile_read": (_i32, [_i32, ctypes.POINTER(_i64), _dp]),
     "sparc_profile_reset": (_i32, []),
-    "sparc_op_set_launch": (_i32, [_vp, _i32, _i32, _i32, _i32]),
+    "sparc_op_set_launch": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32]),
     "sparc_autotune": (_i32, [_vp, _i32, _i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
-                              _dp]),
+                              ctypes.POINTER(_i32), _dp]),
     "sparc_rotate_workspace_bytes": (ctypes.c_size_t, [_i32, _i32]),
     "sparc_server_create": (_i32, [ctypes.POINTER(sparc_server_cfg), ctypes.POINTER(_vp)]),
     "sparc_filter_submit": (_i32, [_vp, ctypes.POINTER(sparc_filter_job), ctypes.POINTER(ctypes.c_uint64)]),
@@ -125,7 +126,8 @@ _SIGS = {
     "sparc_batch_check": (_i32, [_vp, _vp, ctypes.POINTER(_i32)]),
     "sparc_batch_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "sparc_batch_destroy": (_i32, [_vp]),
-    "sparc_step_config": (_i32, [_vp, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "sparc_step_config": (_i32, [_vp, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                 ctypes.POINTER(_i32)]),
 }
 
 
@@ -296,21 +298,34 @@ class Operator:
         # evec is column-major ns x ns: as a torch (ns, ns) row-major tensor it is Q^T
         return theta, evec
 
-    def set_launch(self, dtype_code: int, tile_z: int = 0, tile_y: int = 0, chunk_x: int = 0):
-        check(lib().sparc_op_set_launch(self.handle, dtype_code, tile_z, tile_y, chunk_x), "sparc_op_set_launch")
+    def set_launch(self, dtype_code: int, tile_z: int = 0, tile_y: int = 0, chunk_x: int = 0, col_group: int = 0):
+        check(lib().sparc_op_set_launch(self.handle, dtype_code, tile_z, tile_y, chunk_x, col_group),
+              "sparc_op_set_launch")
 
     def autotune(self, dtype_code: int, ns: int, stream=None):
-        tz, ty, cx = _i32(), _i32(), _i32()
+        """(tile_z, tile_y, chunk_x, col_group, microseconds per step)"""
+        tz, ty, cx, cg = _i32(), _i32(), _i32(), _i32()
         us = ctypes.c_double()
         check(lib().sparc_autotune(self.handle, dtype_code, ns, _stream(stream), ctypes.byref(tz), ctypes.byref(ty),
-                                   ctypes.byref(cx), ctypes.byref(us)), "sparc_autotune")
-        return tz.value, ty.value, cx.value, us.value
+                                   ctypes.byref(cx), ctypes.byref(cg), ctypes.byref(us)), "sparc_autotune")
+        return tz.value, ty.value, cx.value, cg.value, us.value
 
     def step_config(self, dtype_code: int, ns: int):
-        tz, ty, cx = _i32(), _i32(), _i32()
+        """(tile_z, tile_y, chunk_x, col_group)"""
+        tz, ty, cx, cg = _i32(), _i32(), _i32(), _i32()
         check(lib().sparc_step_config(self.handle, dtype_code, ns, ctypes.byref(tz), ctypes.byref(ty),
-                                      ctypes.byref(cx)), "sparc_step_config")
-        return tz.value, ty.value, cx.value
+                                      ctypes.byref(cx), ctypes.byref(cg)), "sparc_step_config")
+        return tz.value, ty.value, cx.value, cg.value
+
+
+def stream_copy(dst, src, stream=None):
+    """dst[:] = src with the library's reference copy kernel (device tensors
+    of equal byte size, a multiple of 16)."""
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("dst and src must have the same byte size")
+    check(lib().sparc_stream_copy(_ptr(dst), _ptr(src), nb, _stream(stream)), "sparc_stream_copy")
+    return dst
 
 
 def select_bounds(theta, nwant: int = 8, shift: float = 0.1, bfactor: float = 1.01, ubound: float = 0.0):

@@ -100,10 +100,14 @@ static int check_block(const sparc_op *op, const void *p, int64_t ld, int ns, co
 
 int launch_h_step(const sparc_op *op, int dtype, const void *yk, int64_t ldk, const void *yprev, int64_t ldp,
                   void *out, int64_t ldo, int ns, void *part, const StepCoef &c, const StepLaunch &L,
-                  hipStream_t stream)
+                  hipStream_t stream, const FLaunch *V)
 {
     int st;
-    if ((st = launch_step_gather(op, dtype, yk, ldk, yprev, ldp, out, ldo, ns, part, c, L, stream))) return st;
+    if (V && V->plan >= 0)
+        st = launch_fstep(op, dtype, *V, yk, ldk, yprev, ldp, out, ldo, ns, part, c, stream);
+    else
+        st = launch_step_gather(op, dtype, yk, ldk, yprev, ldp, out, ldo, ns, part, c, L, stream);
+    if (st) return st;
     return launch_scatter(op, dtype, out, ldo, ns, part, c.alpha, stream);
 }
 
@@ -397,31 +401,43 @@ size_t sparc_workspace_bytes(const sparc_op *op, int32_t dtype, int32_t ns, int3
     return g + align_up((size_t)op->nd * ns * elem_size(dtype));
 }
 
-int sparc_op_set_launch(sparc_op *op, int32_t dtype, int32_t tile_z, int32_t tile_y, int32_t chunk_x)
+int sparc_op_set_launch(sparc_op *op, int32_t dtype, int32_t tile_z, int32_t tile_y, int32_t chunk_x,
+                        int32_t col_group)
 {
     if (!op || (dtype != SPARC_F64 && dtype != SPARC_F32)) return fail(SPARC_E_ARG, "null op or bad dtype");
     if (tile_z <= 0 && tile_y <= 0) {
         op->tune_shape[dtype] = -1;
     } else {
+        // patches of TY x 32 nodes: TY in 16, 32, 64 (FP32) or 8, 16, 32 (FP64)
         int found = -1;
-        for (int s = 0; s < kNumShapes; ++s)
-            if (kShapes[s].tz == tile_z && kShapes[s].ty() == tile_y && found < 0) found = s;
+        for (int p = 0; p < kNumPlans; ++p)
+            if (tile_z == 32 && kPlanTY[p] == tile_y && vec_plan_valid(dtype, p)) found = p;
         if (found < 0) return fail(SPARC_E_ARG, "unsupported tile shape");
         op->tune_shape[dtype] = found;
     }
     op->tune_chunk[dtype] = chunk_x > 0 ? chunk_x : 0;
+    op->tune_group[dtype] = col_group > 0 ? col_group : 0;
     op->tune_ns[dtype] = -1;
     return SPARC_OK;
 }
 
 int sparc_step_config(const sparc_op *op, int32_t dtype, int32_t ns, int32_t *tile_z, int32_t *tile_y,
-                      int32_t *chunk_x)
+                      int32_t *chunk_x, int32_t *col_group)
 {
-    if (!op || ns < 1) return fail(SPARC_E_ARG, "null op or ns < 1");
+    if (!op || ns < 1 || (dtype != SPARC_F64 && dtype != SPARC_F32)) return fail(SPARC_E_ARG, "null op, ns < 1 or bad dtype");
+    const FLaunch V = choose_vec_launch(op, dtype, ns, {});
+    if (V.plan >= 0) {
+        if (tile_z) *tile_z = 32;
+        if (tile_y) *tile_y = kPlanTY[V.plan];
+        if (chunk_x) *chunk_x = V.chunk_x;
+        if (col_group) *col_group = std::min(V.cgroup, ns);
+        return SPARC_OK;
+    }
     StepLaunch L = choose_step_launch(op, dtype, ns);
     if (tile_z) *tile_z = kShapes[L.shape].tz;
     if (tile_y) *tile_y = kShapes[L.shape].ty();
     if (chunk_x) *chunk_x = L.chunk_x;
+    if (col_group) *col_group = 1;
     return SPARC_OK;
 }
 
@@ -438,9 +454,10 @@ int sparc_h_apply(const sparc_op *op, int32_t dtype, const void *X, int64_t ldx,
     if (overlaps(X, bx, Y, by) || overlaps(X, bx, ws, need) || overlaps(Y, by, ws, need))
         return fail(SPARC_E_ALIAS, "X, Y and the workspace must not overlap");
     hipStream_t s = (hipStream_t)stream;
-    StepLaunch L = choose_step_launch(op, dtype, ns);
     StepCoef c{1.0, 0.0, 0.0, 0};
-    return launch_h_step(op, dtype, X, ldx, nullptr, 0, Y, ldy, ns, ws, c, L, s);
+    const FLaunch V = choose_vec_launch(op, dtype, ns, {ldx, ldy});
+    StepLaunch L = choose_step_launch(op, dtype, ns);
+    return launch_h_step(op, dtype, X, ldx, nullptr, 0, Y, ldy, ns, ws, c, L, s, &V);
 }
 
 int sparc_cheb_filter(const sparc_op *op, int32_t dtype, const void *X, int64_t ldx, void *Y, int64_t ldy,
@@ -475,11 +492,13 @@ int sparc_cheb_filter(const sparc_op *op, int32_t dtype, const void *X, int64_t 
     const double c = 0.5 * (b + a);
     const double sigma1 = e / (a0 - c);
     const double tau = 2.0 / sigma1;
+    // one kernel family for every step of the filter
+    const FLaunch V = choose_vec_launch(op, dtype, ns, {ldx, ldy, ldw});
     StepLaunch L = choose_step_launch(op, dtype, ns);
 
     // Y_1 = (sigma_1/e)(H - cI) X
     StepCoef c1{sigma1 / e, 0.0, c, 0};
-    if ((st = launch_h_step(op, dtype, X, ldx, nullptr, 0, P, ldP, ns, G, c1, L, s))) return st;
+    if ((st = launch_h_step(op, dtype, X, ldx, nullptr, 0, P, ldP, ns, G, c1, L, s, &V))) return st;
 
     double sigma = sigma1;
     for (int k = 1; k < m; ++k) {
@@ -491,7 +510,7 @@ int sparc_cheb_filter(const sparc_op *op, int32_t dtype, const void *X, int64_t 
         void *out = ((k + 1) & 1) ? P : Q;
         const int64_t ldo = ((k + 1) & 1) ? ldP : ldQ;
         StepCoef ck{2.0 * sigma_next / e, sigma * sigma_next, c, 1};
-        if ((st = launch_h_step(op, dtype, yk, ldk, yprev, ldp, out, ldo, ns, G, ck, L, s))) return st;
+        if ((st = launch_h_step(op, dtype, yk, ldk, yprev, ldp, out, ldo, ns, G, ck, L, s, &V))) return st;
         sigma = sigma_next;
     }
     return SPARC_OK;

@@ -2,8 +2,8 @@
 //
 // Every filter of the batch is cut into work items of the same three kinds a
 // standalone filter launches per degree step k (Sec. 3.4, Alg. 2):
-//   A(k): projector-gather items (atom, split; all column blocks) and stencil
-//         items (patch, x-chunk, group of 8 columns) of step k;
+//   A(k): projector-gather items (atom, split; all column blocks) and vector
+//         stencil items (patch, x-chunk, group of 8 columns) of step k;
 //   B(k): projector-scatter items (node block; all column groups) of step k.
 // Dependencies per cluster: A(k) needs B(k-1) complete (A(k-1) when the cluster
 // has no atoms), B(k) needs A(k) complete.  Items are numbered in level order
@@ -17,8 +17,11 @@
 // Completion is published with a device-scope release (barrier, then one
 // release increment of the counter) and observed with a device-scope acquire, so
 // data written on one XCD is read correctly on another.  Each item runs exactly
-// the arithmetic of the corresponding standalone kernel, so a cluster's result
-// is bit-identical alone and in the batch.
+// the arithmetic of the corresponding standalone kernel (the stencil items use
+// the 256-thread vector patch of their dtype: 32 x 32 FP32, 16 x 32 FP64, whose
+// per-point sums equal those of every other patch), so a cluster's result is
+// bit-identical alone and in the batch.  Batched modes need grids and leading
+// dimensions the vector kernels take.
 //
 // Modes: 0 = persistent kernel captured with the counter reset in a HIP graph
 // (replayed on later runs); 1 = the same two launches without a graph;
@@ -30,8 +33,8 @@
 #include <cstring>
 #include <new>
 
+#include "fstep_kernel.hpp"
 #include "nonlocal_kernel.hpp"
-#include "step_kernel.hpp"
 
 namespace sparc {
 
@@ -53,7 +56,7 @@ struct BatchClusterDev {
     void *P, *Q;  // Y_j lands in P for odd j, in Q for even j
     void *G;      // gather partials
     long long ldx, ldp, ldq;
-    // stencil launch geometry (32 x 16 patches)
+    // stencil geometry (256-thread vector patches)
     int tiles_y, tiles_z, nchunks, chunk_x;
     // items per step
     int nG, nS, nC, ncb, ncg;
@@ -79,12 +82,21 @@ struct BatchArgs {
     int waits;       // persistent mode: 1
 };
 
-constexpr int kBatchTZ = 32, kBatchRY = 2, kBatchNT = 256;
+constexpr int kBatchNT = 256;
+constexpr int kBatchPlan[2] = {1, 2};  // per dtype (F64, F32): the 256-thread patch heights
 
 template <typename T>
-using BStep = StepKernel<T, kBatchTZ, kBatchRY, kBatchNT, true>;
-template <typename T>
-using BStep0 = StepKernel<T, kBatchTZ, kBatchRY, kBatchNT, false>;
+struct BatchTY;
+template <>
+struct BatchTY<float> {
+    static constexpr int TY = 32;
+};
+template <>
+struct BatchTY<double> {
+    static constexpr int TY = 16;
+};
+template <typename T, bool PREV>
+using BStep = FStep<T, BatchTY<T>::TY, PREV, false>;
 
 constexpr int kBatchColGroup = 8;  // columns per stencil item
 
@@ -133,9 +145,9 @@ __device__ __forceinline__ void do_gather(const BatchClusterDev &c, int k, int l
 template <typename T, bool PREV>
 __device__ __forceinline__ void do_step(const BatchClusterDev &c, int k, int local, char *smem)
 {
-    using K = StepKernel<T, kBatchTZ, kBatchRY, kBatchNT, PREV>;
+    using K = BStep<T, PREV>;
     const StepSel sel = select_buffers(c, k);
-    StepArgs<T> a;
+    FStepArgs<T> a;
     a.yk = (const T *)sel.yk;
     a.yprev = (const T *)sel.yprev;
     a.out = (T *)sel.out;
@@ -152,6 +164,8 @@ __device__ __forceinline__ void do_step(const BatchClusterDev &c, int k, int loc
     a.chunk_x = c.chunk_x;
     a.nblocks = c.nS;
     a.remap = 0;
+    a.ns = c.ns;
+    a.cgroup = 1;
     a.c0 = (T)c.c0;
     for (int p = 0; p < kMaxRadius; ++p) a.cp[p] = (T)c.cp[p];
     const double *cf = c.coef + 3 * k;
@@ -164,7 +178,7 @@ __device__ __forceinline__ void do_step(const BatchClusterDev &c, int k, int loc
 #pragma unroll 1
     for (int col = g * kBatchColGroup; col < c1; ++col) {
         K s(a);
-        s.run(col * per_col + tc, (T(*)[K::SY * K::SZ])smem);
+        s.run(col * per_col + tc, *(typename K::Shared *)smem);
         __syncthreads();
     }
 }
@@ -223,12 +237,15 @@ __device__ inline int find_segment(const BatchSegment *seg, int nseg, int t)
     return lo;
 }
 
-constexpr size_t kBatchLds = sizeof(double) * 2 * BStep<double>::SY * BStep<double>::SZ;
+constexpr size_t cmax(size_t x, size_t y) { return x > y ? x : y; }
+constexpr size_t kBatchLds = cmax(sizeof(BStep<float, true>::Shared), sizeof(BStep<double, true>::Shared));
 
 template <bool F32, bool F64>
 __global__ void __launch_bounds__(kBatchNT) batch_kernel(const BatchArgs args)
 {
-    __shared__ __align__(16) char smem[kBatchLds];
+    // the stencil planes, the gather tile or the scatter table
+    __shared__ __align__(16) char smem[cmax(cmax(kBatchLds, sizeof(double) * 4 * 16 * 16),
+                                            sizeof(double) * kScatterSlots * kMaxProj * kScatterCols)];
     __shared__ int s_t;
     __shared__ int s_go;
     const int tid = threadIdx.x;
@@ -471,15 +488,23 @@ int sparc_batch_create(const sparc_batch_job *jobs, int32_t njobs, int32_t mode,
         c.ldp = odd ? j.ldy : op->nd;
         c.ldq = odd ? op->nd : j.ldy;
         c.G = (char *)b->d_work + goff[i];
-        // stencil geometry: 32 x 16 patches; x is split only when a cluster
-        // would have fewer than ~64 stencil items per step
-        c.tiles_y = (c.n2 + 15) / 16;
-        c.tiles_z = (c.n3 + 31) / 32;
-        const long long per = (long long)c.tiles_y * c.tiles_z * ((j.ns + kBatchColGroup - 1) / kBatchColGroup);
-        int nch = (int)std::max<long long>(1, std::min<long long>((64 + per - 1) / per, c.n1 / 8));
-        if (tune_applies(op, j.dtype, j.ns) && op->tune_chunk[j.dtype] > 0) nch = (c.n1 + op->tune_chunk[j.dtype] - 1) / op->tune_chunk[j.dtype];
-        c.chunk_x = (c.n1 + nch - 1) / nch;
-        c.nchunks = (c.n1 + c.chunk_x - 1) / c.chunk_x;
+        // stencil geometry: the dtype's 256-thread vector patch and the
+        // standalone filter's x split for it
+        if (mode != 3) {
+            const FLaunch V = choose_vec_launch(op, j.dtype, j.ns, {j.ldx, j.ldy, op->nd});
+            if (V.plan < 0)
+                return cleanup(fail(SPARC_E_SHAPE, "job " + std::to_string(i) +
+                                                       ": batched modes need the vector step kernels (z extent and "
+                                                       "leading dimensions multiples of 4 FP32 / 2 FP64 values)"));
+            const FLaunch B = V.plan == kBatchPlan[j.dtype] ? V : vec_launch_plan(op, j.dtype, j.ns, kBatchPlan[j.dtype]);
+            const int ty = kPlanTY[B.plan];
+            c.tiles_y = (c.n2 + ty - 1) / ty;
+            c.tiles_z = (c.n3 + 31) / 32;
+            c.chunk_x = B.chunk_x;
+            c.nchunks = B.nchunks;
+        } else {
+            c.tiles_y = c.tiles_z = c.chunk_x = c.nchunks = 1;
+        }
         c.ncb = (j.ns + 15) / 16;
         c.ncg = (j.ns + kScatterCols - 1) / kScatterCols;
         const long long nS = (long long)c.tiles_y * c.tiles_z * c.nchunks * ((j.ns + kBatchColGroup - 1) / kBatchColGroup);

@@ -1,0 +1,12 @@
+// Vector step kernels for double blocks on patches of 8 x 32 nodes (see fstep.hip).
+#include "fstep_launch.hpp"
+
+namespace sparc {
+
+int fstep_f64_ty8(const FStepArgs<double> &a, const GatherArgs<double, double> &g, int natoms, int ncb, int nitems, int ngb,
+                    bool prev, bool strm, hipStream_t s)
+{
+    return fstep_dispatch<double, 8>(a, g, natoms, ncb, nitems, ngb, prev, strm, s);
+}
+
+}  // namespace sparc

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <initializer_list>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -29,6 +30,10 @@ struct AtomDev {
     long long chi0;   // offset of the atom's chi block (nproj * nbox values)
 };
 
+// Patch heights of the vector step kernels (patches of TY x 32 nodes in y, z)
+constexpr int kNumPlans = 4;
+constexpr int kPlanTY[kNumPlans] = {8, 16, 32, 64};
+
 // Tile shapes of the fused step kernel: a workgroup of nt threads owns a
 // TY x TZ patch of the (y, z) plane and streams it along x.  TZ lanes run
 // along z; each thread owns RY consecutive rows of y.
@@ -36,7 +41,7 @@ struct TileShape {
     int tz, ry, nt;
     int ty() const { return ry * (nt / tz); }
 };
-constexpr int kNumShapes = 6;
+constexpr int kNumShapes = 2;
 extern const TileShape kShapes[kNumShapes];
 
 }  // namespace sparc
@@ -79,6 +84,7 @@ struct sparc_op {
     int tune_shape[2] = {-1, -1};
     int tune_chunk[2] = {0, 0};
     int tune_ns[2] = {-1, -1};  // block width the launch choice was tuned for; -1: every width
+    int tune_group[2] = {0, 0};  // column group of the vector step (0 = library choice)
 };
 
 namespace sparc {
@@ -122,6 +128,27 @@ inline size_t gather_bytes(const sparc_op *op, int dtype, int ns)
                     (dtype == SPARC_F64 ? 8 : 4));
 }
 
+// Launch of the vector step kernels (fstep.hip): patch height TY =
+// kPlanTY[plan], x split and column group.  plan < 0: the grid or a leading
+// dimension rules the vector kernels out.
+struct FLaunch {
+    int plan = -1;
+    int chunk_x = 0, nchunks = 0;
+    int cgroup = 1;  // columns of one patch on consecutive workgroups
+};
+constexpr int kMaxChunks = 16;  // most x-chunks of a vector step launch
+
+// is plan a patch height offered for dtype
+bool vec_plan_valid(int dtype, int plan);
+// vector launch for a block of ns columns whose leading dimensions are lds
+FLaunch choose_vec_launch(const sparc_op *op, int dtype, int ns, std::initializer_list<int64_t> lds);
+// the default x split of patch height `plan` (no tuning applied)
+FLaunch vec_launch_plan(const sparc_op *op, int dtype, int ns, int plan);
+// enqueue a vector step; with part (and atoms) the same launch gathers the
+// projections of yk into part (the standalone gather's layout)
+int launch_fstep(const sparc_op *op, int dtype, const FLaunch &L, const void *yk, int64_t ldk, const void *yprev,
+                 int64_t ldp, void *out, int64_t ldo, int ns, void *part, const StepCoef &c, hipStream_t stream);
+
 // enqueue the projector gather: split partial sums of chi_Jp^T Y(:,c) per atom
 int launch_gather(const sparc_op *op, int dtype, const void *Y, int64_t ldy, int ns, void *part,
                   hipStream_t stream);
@@ -154,10 +181,12 @@ int launch_step_gather(const sparc_op *op, int dtype, const void *yk, int64_t ld
                        void *out, int64_t ldo, int ns, void *part, const StepCoef &c, const StepLaunch &L,
                        hipStream_t stream);
 
-// the full operator step: gather(yk), local step, scatter(alpha)
+// the full operator step: gather(yk) and the local step in one launch (the
+// vector kernels when V is given and usable, else the scalar ones), then the
+// scatter(alpha)
 int launch_h_step(const sparc_op *op, int dtype, const void *yk, int64_t ldk, const void *yprev, int64_t ldp,
                   void *out, int64_t ldo, int ns, void *part, const StepCoef &c, const StepLaunch &L,
-                  hipStream_t stream);
+                  hipStream_t stream, const FLaunch *V = nullptr);
 
 // small generalized eigensolver (n <= 64) in one workgroup: theta ascending,
 // evec column-major and M-orthonormal; info = 0 or the failing Cholesky column

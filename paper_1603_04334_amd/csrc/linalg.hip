@@ -359,10 +359,12 @@ __global__ void f64_to_f32_dense(const double *src, float *dst, long long n)
 // M_s = Y^T Y and H_s = Y^T (HY) in FP64 on the matrix cores
 // (v_mfma_f64_16x16x4f64).  The contraction runs over the N_d grid points,
 // which are split into chunks; a workgroup owns one 64 x 64 tile pair of
-// (M_s, H_s) for one chunk, stages 32-point slices of the three column
-// panels in LDS (coalesced along the contiguous grid axis) and writes its
-// partial tiles, which a second kernel sums in chunk order.  Each of the four
-// waves owns a 32 x 32 quarter of both tiles (2 x 2 MFMA blocks each).
+// (M_s, H_s) on or above the diagonal for one chunk (both matrices are
+// symmetric: the lower tiles are copies), stages 32-point slices of the three
+// column panels in LDS (coalesced along the contiguous grid axis) and writes
+// its partial tiles, which a second kernel sums in chunk order; the upper
+// triangle is then mirrored.  Each of the four waves owns a 32 x 32 quarter of
+// both tiles (2 x 2 MFMA blocks each).
 
 constexpr int kRrTile = 64;
 constexpr int kRrK = 32;
@@ -386,7 +388,15 @@ __global__ void __launch_bounds__(256) rr_project_kernel(const TY *__restrict__ 
     __shared__ double sA[kRrTile][kRrK + 1];  // Y columns of the row tile, [col][k]
     __shared__ double sB[kRrTile][kRrK + 1];  // Y columns of the column tile
     __shared__ double sH[kRrTile][kRrK + 1];  // HY columns of the column tile
-    const int ti = blockIdx.y, tj = blockIdx.z;
+    // tile pair (ti <= tj) number blockIdx.y, pairs in row order: both
+    // matrices are symmetric, so only the upper tiles are formed
+    const int nt = (ns + kRrTile - 1) / kRrTile;
+    int ti = 0, rem = blockIdx.y;
+    while (rem >= nt - ti) {
+        rem -= nt - ti;
+        ++ti;
+    }
+    const int tj = ti + rem;
     const long long k0 = blockIdx.x * kchunk;
     const long long k1 = (k0 + kchunk < nd) ? k0 + kchunk : nd;
     const int tid = threadIdx.x;
@@ -464,29 +474,28 @@ __global__ void __launch_bounds__(256) rr_project_kernel(const TY *__restrict__ 
             }
 }
 
-// Ms, Hs (column-major ns x ns) = sum over chunks of the partial tiles, in chunk order
+// Ms, Hs (column-major ns x ns) = sum over chunks of the partial tiles, in
+// chunk order, for the entries of the upper tiles (row tile <= column tile)
 __global__ void rr_reduce_kernel(const double *partial, int nchunks, int ns, double *Ms, double *Hs)
 {
     const long long mat = (long long)ns * ns;
     const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (e >= 2 * mat) return;
     const long long which = e / mat, off = e - which * mat;
+    const int row = (int)(off % ns), col = (int)(off / ns);
+    if (row / kRrTile > col / kRrTile) return;
     double s = 0.0;
 #pragma unroll 16
     for (int c = 0; c < nchunks; ++c) s += partial[((long long)c * 2 + which) * mat + off];
     (which == 0 ? Ms : Hs)[off] = s;
 }
 
-// symmetrise an ns x ns matrix in place: A = (A + A^T)/2
-__global__ void symmetrize(double *A, int ns)
+// the lower triangle of an ns x ns column-major matrix copied from the upper
+__global__ void mirror_upper(double *A, int ns)
 {
     const int i = blockIdx.y * blockDim.y + threadIdx.y;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < ns && j < ns && i < j) {
-        const double v = 0.5 * (A[(long long)j * ns + i] + A[(long long)i * ns + j]);
-        A[(long long)j * ns + i] = v;
-        A[(long long)i * ns + j] = v;
-    }
+    if (i < ns && j < ns && i < j) A[(long long)i * ns + j] = A[(long long)j * ns + i];
 }
 
 static dim3 stream_grid(long long n)
@@ -817,8 +826,10 @@ int sparc_lanczos(const sparc_op *op, int32_t k, const double *v0, double *alpha
 
 static long long rr_chunk(long long nd, int ns)
 {
-    // about 256 workgroups in total, chunks a multiple of the staged slice
-    const long long tiles = (long long)((ns + kRrTile - 1) / kRrTile) * ((ns + kRrTile - 1) / kRrTile);
+    // about 512 workgroups in total (upper tile pairs x chunks), chunks a
+    // multiple of the staged slice
+    const long long nt = (ns + kRrTile - 1) / kRrTile;
+    const long long tiles = nt * (nt + 1) / 2;
     long long nch = std::max<long long>(1, 512 / tiles);
     long long c = (nd + nch - 1) / nch;
     c = (c + kRrK - 1) / kRrK * kRrK;
@@ -871,9 +882,10 @@ int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_
     const long long kc = rr_chunk(nd, ns);
     const int nch = (int)((nd + kc - 1) / kc);
     const int nt = (ns + kRrTile - 1) / kRrTile;
-    const dim3 pg(nch, nt, nt);
+    const dim3 pg(nch, nt * (nt + 1) / 2, 1);
     if (dtype == SPARC_F64) {
-        if ((st = launch_h_step(op, SPARC_F64, Y, ldy, nullptr, 0, HY, nd, ns, G, hc, L, s))) return st;
+        const FLaunch V = choose_vec_launch(op, SPARC_F64, ns, {ldy, nd});
+        if ((st = launch_h_step(op, SPARC_F64, Y, ldy, nullptr, 0, HY, nd, ns, G, hc, L, s, &V))) return st;
         hipLaunchKernelGGL(rr_project_kernel<double>, pg, dim3(256), 0, s, (const double *)Y, (long long)ldy,
                            (const double *)HY, nd, nd, ns, kc, partial);
     } else {
@@ -888,8 +900,8 @@ int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_
     const long long tot = 2LL * ns * ns;
     hipLaunchKernelGGL(rr_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, partial, nch, ns, Ms, Hs);
     dim3 tb(16, 16), tg((ns + 15) / 16, (ns + 15) / 16);
-    hipLaunchKernelGGL(symmetrize, tg, tb, 0, s, Hs, ns);
-    hipLaunchKernelGGL(symmetrize, tg, tb, 0, s, Ms, ns);
+    hipLaunchKernelGGL(mirror_upper, tg, tb, 0, s, Hs, ns);
+    hipLaunchKernelGGL(mirror_upper, tg, tb, 0, s, Ms, ns);
     SPARC_HIP(hipGetLastError());
 
     if (ns <= 64) {
@@ -953,6 +965,36 @@ int sparc_rotate(int32_t dtype, const void *Y, int64_t ldy, int64_t nd, int32_t 
     hipStream_t s = (hipStream_t)stream;
     const unsigned gx = (unsigned)((nd + 255) / 256);
     const int ldq = rot_ldq(ns);
+    // Blocks wider than one column block of the kernel below would re-read Y
+    // once per block of output columns; the product is then a plain GEMM on
+    // the matrix cores (rocBLAS, atomics off: deterministic).
+    const bool gemm = ns > (dtype == SPARC_F64 ? RotTile<double>::cols : RotTile<float>::cols) &&
+                      nd <= 0x7fffffffLL && ldy <= 0x7fffffffLL && ldo <= 0x7fffffffLL;
+    if (gemm) {
+        BlasLease lease(s);
+        if (!lease.h) return fail(SPARC_E_HIP, "rocblas_create_handle failed");
+        rocblas_status rs;
+        if (dtype == SPARC_F64) {
+            hipLaunchKernelGGL(pad_rotation<double>, stream_grid((long long)ldq * ns), dim3(256), 0, s, Q, ns,
+                               (double *)ws, ldq, ns);
+            const double one = 1.0, zero = 0.0;
+            rs = rocblas_dgemm(lease.h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)nd, ns, ns, &one,
+                               (const double *)Y, (rocblas_int)ldy, (const double *)ws, ldq, &zero, (double *)out,
+                               (rocblas_int)ldo);
+        } else {
+            hipLaunchKernelGGL(pad_rotation<float>, stream_grid((long long)ldq * ns), dim3(256), 0, s, Q, ns,
+                               (float *)ws, ldq, ns);
+            const float one = 1.0f, zero = 0.0f;
+            rs = rocblas_sgemm(lease.h, rocblas_operation_none, rocblas_operation_none, (rocblas_int)nd, ns, ns, &one,
+                               (const float *)Y, (rocblas_int)ldy, (const float *)ws, ldq, &zero, (float *)out,
+                               (rocblas_int)ldo);
+        }
+        const hipError_t after = hipGetLastError();
+        if (rs != rocblas_status_success)
+            return fail(SPARC_E_HIP, std::string("rocBLAS GEMM of the rotation failed: ") + rocblas_status_to_string(rs));
+        if (after != hipSuccess) return fail(SPARC_E_HIP, std::string("rotation: ") + hipGetErrorString(after));
+        return SPARC_OK;
+    }
     if (dtype == SPARC_F64) {
         const int ncp = rot_ncols<double>(ns);
         hipLaunchKernelGGL(pad_rotation<double>, stream_grid((long long)ldq * ncp), dim3(256), 0, s, Q, ns,

@@ -13,8 +13,8 @@
 //    over the unique nodes covered by at least one cube, grouped in blocks of
 //    at most 256 nodes that touch at most kScatterSlots atoms (tables built at
 //    operator creation).  A workgroup first finishes h^3 gamma S for its
-//    block's atoms and four columns into LDS (split partials summed in order),
-//    then each thread updates one node for the four columns, atoms in a fixed
+//    block's atoms and eight columns into LDS (split partials summed in order),
+//    then each thread updates one node for the eight columns, atoms in a fixed
 //    order: deterministic even where cubes overlap.
 //
 // MFMA operand layout of the 16x16x4 instructions (64 lanes, lane = i + 16k,

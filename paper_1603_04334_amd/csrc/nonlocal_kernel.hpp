@@ -110,7 +110,7 @@ __device__ __forceinline__ void gather_item(const GatherArgs<T, TI> &g, int atom
     }
 }
 
-constexpr int kScatterCols = 4;
+constexpr int kScatterCols = 8;  // columns per scatter workgroup (the table of h^3 gamma S is built once for them)
 
 template <typename T>
 struct ScatterArgs {

@@ -44,8 +44,10 @@
 
 namespace sparc {
 
-const TileShape kShapes[kNumShapes] = {{32, 2, 256}, {32, 2, 512}, {32, 2, 768}, {64, 2, 256},
-                                       {64, 2, 512}, {32, 4, 256}};
+// scalar step kernels: 32 x 16 patches of 256 threads (filters and H X that
+// the vector kernels cannot take), 32 x 32 patches of 512 threads (FP64 H on
+// FP32 blocks)
+const TileShape kShapes[kNumShapes] = {{32, 2, 256}, {32, 2, 512}};
 
 // H v for one FP64 vector in one launch: the first ngather workgroups gather
 // the projections of v (atom i % natoms, split i / natoms, as the standalone
@@ -91,15 +93,10 @@ static int pick_taller(const sparc_op *op, int shape, double speed)
 
 StepLaunch choose_step_launch(const sparc_op *op, int dtype, int ns)
 {
+    (void)dtype;
     StepLaunch L;
-    // 32 x 16 patches of 256 threads measured fastest in FP64 on the 96^3 and
-    // larger grids; in FP32, 32 x 48 patches of 768 threads run about 4.5%
-    // faster per point
-    L.shape = dtype == SPARC_F32 ? pick_taller(op, 2, 0.955) : 0;
-    const bool tuned = tune_applies(op, dtype, ns);
-    if (tuned && op->tune_shape[dtype] >= 0) L.shape = op->tune_shape[dtype];
+    L.shape = 0;
     L.chunk_x = default_chunk(op, L.shape, ns);
-    if (tuned && op->tune_chunk[dtype] > 0) L.chunk_x = std::min(op->n[0], op->tune_chunk[dtype]);
     return L;
 }
 

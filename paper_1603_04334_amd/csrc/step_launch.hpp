@@ -166,10 +166,6 @@ int launch_step_t(const sparc_op *op, const void *yk, int64_t ldk, const void *y
     switch (L.shape) {
         case 0: return launch_typed<T, 32, 2, 256, TI>(a, prev, strm, stream, &gp);
         case 1: return launch_typed<T, 32, 2, 512, TI>(a, prev, strm, stream, &gp);
-        case 2: return launch_typed<T, 32, 2, 768, TI>(a, prev, strm, stream, &gp);
-        case 3: return launch_typed<T, 64, 2, 256, TI>(a, prev, strm, stream, &gp);
-        case 4: return launch_typed<T, 64, 2, 512, TI>(a, prev, strm, stream, &gp);
-        case 5: return launch_typed<T, 32, 4, 256, TI>(a, prev, strm, stream, &gp);
     }
     return fail(SPARC_E_ARG, "unknown tile shape");
 }

@@ -1,9 +1,12 @@
-// Autotuner of the fused step kernel's launch: for one operator, dtype and
-// column count it times every tile shape and a few x-chunk lengths on scratch
-// blocks (HIP events around repeated recurrence-step launches) and keeps the
-// fastest.  Choices are cached per (grid, columns, dtype) in the process and,
-// when SPARC_TUNE_CACHE names a file, in that text file (one line per entry:
-// n1 n2 n3 ns dtype shape chunk microseconds).
+// Autotuner of the vector step launch: for one operator, dtype and column
+// count it times every patch height, a few x splits and column groups of what
+// a filter step enqueues (the fused stencil / potential / recurrence pass with
+// the projector gather of its input in the same launch, then the projector
+// scatter) on scratch blocks, with HIP events around repeated steps, and keeps
+// the fastest.  Choices are cached per
+// (grid, atoms, projectors, columns, dtype) in the process and, when
+// SPARC_TUNE_CACHE names a file, in that text file (one line per entry:
+// n1 n2 n3 natoms nproj ns dtype plan chunk group microseconds).
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -14,9 +17,9 @@
 namespace sparc {
 namespace {
 
-using Key = std::tuple<int, int, int, int, int>;
+using Key = std::tuple<int, int, int, int, int, int, int>;
 struct Choice {
-    int shape, chunk;
+    int plan, chunk, group;
     double us;
 };
 std::mutex g_tune_mu;
@@ -31,10 +34,10 @@ void load_cache()
     if (!path) return;
     FILE *f = std::fopen(path, "r");
     if (!f) return;
-    int n1, n2, n3, ns, dt, sh, ch;
+    int n1, n2, n3, na, np, ns, dt, pl, ch, gr;
     double us;
-    while (std::fscanf(f, "%d %d %d %d %d %d %d %lf", &n1, &n2, &n3, &ns, &dt, &sh, &ch, &us) == 8)
-        if (sh >= 0 && sh < kNumShapes && ch > 0) g_tune[Key(n1, n2, n3, ns, dt)] = {sh, ch, us};
+    while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %lf", &n1, &n2, &n3, &na, &np, &ns, &dt, &pl, &ch, &gr, &us) == 11)
+        if (pl >= 0 && pl < kNumPlans && ch > 0 && gr > 0) g_tune[Key(n1, n2, n3, na, np, ns, dt)] = {pl, ch, gr, us};
     std::fclose(f);
 }
 
@@ -44,8 +47,8 @@ void store_cache(const Key &k, const Choice &c)
     if (!path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%d %d %d %d %d %d %d %.3f\n", std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k),
-                 std::get<4>(k), c.shape, c.chunk, c.us);
+    std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %.3f\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+                 std::get<3>(k), std::get<4>(k), std::get<5>(k), std::get<6>(k), c.plan, c.chunk, c.group, c.us);
     std::fclose(f);
 }
 
@@ -55,78 +58,99 @@ void store_cache(const Key &k, const Choice &c)
 using namespace sparc;
 
 extern "C" int sparc_autotune(sparc_op *op, int32_t dtype, int32_t ns, void *stream, int32_t *tile_z, int32_t *tile_y,
-                              int32_t *chunk_x, double *best_us)
+                              int32_t *chunk_x, int32_t *col_group, double *best_us)
 {
     if (!op || ns < 1 || (dtype != SPARC_F64 && dtype != SPARC_F32)) return fail(SPARC_E_ARG, "bad arguments");
     hipStream_t s = (hipStream_t)stream;
-    const Key key(op->n[0], op->n[1], op->n[2], ns, dtype);
-    Choice best{-1, 0, 1e30};
+    if (choose_vec_launch(op, dtype, ns, {}).plan < 0)
+        return fail(SPARC_E_SHAPE, "the vector step kernels cannot take this grid (nothing to tune)");
+    const Key key(op->n[0], op->n[1], op->n[2], op->natoms, op->nproj_total, ns, dtype);
+    Choice best{-1, 0, 1, 1e30};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         load_cache();
         auto it = g_tune.find(key);
         if (it != g_tune.end()) best = it->second;
     }
-    if (best.shape < 0) {
+    if (best.plan < 0) {
         const size_t es = elem_size(dtype);
         const size_t blk = (size_t)op->nd * ns * es;
-        void *X = nullptr, *Y = nullptr, *P = nullptr;
-        if (hipMalloc(&X, blk) != hipSuccess || hipMalloc(&Y, blk) != hipSuccess || hipMalloc(&P, blk) != hipSuccess) {
+        const int saved_shape = op->tune_shape[dtype], saved_chunk = op->tune_chunk[dtype];
+        const int saved_ns = op->tune_ns[dtype], saved_group = op->tune_group[dtype];
+        const int lo = dtype == SPARC_F64 ? 0 : 1;
+        const int n1 = op->n[0];
+        const int chunks[] = {0, n1, (n1 + 1) / 2, (n1 + 3) / 4, (n1 + 7) / 8};
+        const size_t pb = std::max<size_t>(gather_bytes(op, dtype, ns), 256);
+        void *X = nullptr, *Y = nullptr, *Pv = nullptr, *G = nullptr;
+        if (hipMalloc(&X, blk) != hipSuccess || hipMalloc(&Y, blk) != hipSuccess || hipMalloc(&Pv, blk) != hipSuccess ||
+            hipMalloc(&G, pb) != hipSuccess) {
             (void)hipFree(X);
             (void)hipFree(Y);
-            (void)hipFree(P);
+            (void)hipFree(Pv);
+            (void)hipFree(G);
             return fail(SPARC_E_NOMEM, "autotune scratch allocation failed");
         }
+        op->tune_ns[dtype] = ns;
         (void)hipMemsetAsync(X, 0, blk, s);
-        (void)hipMemsetAsync(P, 0, blk, s);
+        (void)hipMemsetAsync(Pv, 0, blk, s);
+        (void)hipMemsetAsync(G, 0, pb, s);
         hipEvent_t e0, e1;
         (void)hipEventCreate(&e0);
         (void)hipEventCreate(&e1);
-        const int saved_shape = op->tune_shape[dtype], saved_chunk = op->tune_chunk[dtype];
-        const int saved_ns = op->tune_ns[dtype];
-        op->tune_ns[dtype] = ns;
-        const int n1 = op->n[0];
-        const int chunks[] = {0, n1, (n1 + 1) / 2, (n1 + 3) / 4, (n1 + 7) / 8};
         StepCoef cf{1.0, 0.5, 0.0, 1};
+        const StepLaunch Ls = choose_step_launch(op, dtype, ns);
         int st = SPARC_OK;
-        for (int sh = 0; sh < kNumShapes && st == SPARC_OK; ++sh) {
+        const int groups[] = {1, 4, 8, 16};
+        for (int p = lo; p < lo + 3 && st == SPARC_OK; ++p) {
             for (int ci = 0; ci < 5 && st == SPARC_OK; ++ci) {
                 if (chunks[ci] > 0 && chunks[ci] < 4) continue;
-                op->tune_shape[dtype] = sh;
-                op->tune_chunk[dtype] = chunks[ci];
-                const StepLaunch L = choose_step_launch(op, dtype, ns);
-                if ((st = launch_step(op, dtype, X, op->nd, P, op->nd, Y, op->nd, ns, cf, L, s))) break;
-                (void)hipEventRecord(e0, s);
-                const int reps = 3;
-                for (int r = 0; r < reps && st == SPARC_OK; ++r)
-                    st = launch_step(op, dtype, X, op->nd, P, op->nd, Y, op->nd, ns, cf, L, s);
-                (void)hipEventRecord(e1, s);
-                if (hipEventSynchronize(e1) != hipSuccess) st = fail(SPARC_E_HIP, "autotune timing failed");
-                float ms = 0;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                const double us = ms * 1e3 / reps;
-                if (st == SPARC_OK && us < best.us) best = {sh, L.chunk_x, us};
+                for (int gi = 0; gi < 4 && st == SPARC_OK; ++gi) {
+                    if (groups[gi] > ns && gi > 0) continue;
+                    op->tune_shape[dtype] = p;
+                    op->tune_chunk[dtype] = chunks[ci];
+                    op->tune_group[dtype] = groups[gi];
+                    const FLaunch L = choose_vec_launch(op, dtype, ns, {});
+                    if (L.plan != p) continue;
+                    // a filter step as the filter runs it: the step with the
+                    // gather of its input in one launch, then the scatter
+                    if ((st = launch_h_step(op, dtype, X, op->nd, Pv, op->nd, Y, op->nd, ns, G, cf, Ls, s, &L))) break;
+                    (void)hipEventRecord(e0, s);
+                    const int reps = 3;
+                    for (int r = 0; r < reps && st == SPARC_OK; ++r)
+                        st = launch_h_step(op, dtype, X, op->nd, Pv, op->nd, Y, op->nd, ns, G, cf, Ls, s, &L);
+                    (void)hipEventRecord(e1, s);
+                    if (hipEventSynchronize(e1) != hipSuccess) st = fail(SPARC_E_HIP, "autotune timing failed");
+                    float ms = 0;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    const double us = ms * 1e3 / reps;
+                    if (st == SPARC_OK && us < best.us) best = {p, L.chunk_x, L.cgroup, us};
+                }
             }
         }
         op->tune_shape[dtype] = saved_shape;
         op->tune_chunk[dtype] = saved_chunk;
         op->tune_ns[dtype] = saved_ns;
+        op->tune_group[dtype] = saved_group;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         (void)hipFree(X);
         (void)hipFree(Y);
-        (void)hipFree(P);
+        (void)hipFree(Pv);
+        (void)hipFree(G);
         if (st) return st;
+        if (best.plan < 0) return fail(SPARC_E_SHAPE, "no usable patch height");
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune[key] = best;
         store_cache(key, best);
     }
-    op->tune_shape[dtype] = best.shape;
+    op->tune_shape[dtype] = best.plan;
     op->tune_chunk[dtype] = best.chunk;
+    op->tune_group[dtype] = best.group;
     op->tune_ns[dtype] = ns;  // the choice holds for this block width only
-    if (tile_z) *tile_z = kShapes[best.shape].tz;
-    if (tile_y) *tile_y = kShapes[best.shape].ty();
+    if (tile_z) *tile_z = 32;
+    if (tile_y) *tile_y = kPlanTY[best.plan];
     if (chunk_x) *chunk_x = best.chunk;
+    if (col_group) *col_group = best.group;
     if (best_us) *best_us = best.us;
     return SPARC_OK;
 }

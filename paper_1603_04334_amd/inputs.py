@@ -207,6 +207,23 @@ def orbitals(nd: int, ns: int, seed: int, cols: Optional[Sequence[int]] = None,
     return out
 
 
+def device_orbitals(nd: int, ns: int, seed: int, dtype=None, device: str = "cuda"):
+    """N(0,1) orbital block of shape (ns, nd) drawn on the device by torch's
+    seeded generator (Philox), for blocks too large to draw on the host
+    (600 columns of a 160^3 grid are 2.5e9 values).  The same seed gives the
+    same block; the FP32 block is drawn in FP32 and the FP64 block is its
+    exact widening, so both dtypes start from the same values.  Columns are
+    copied to the host where a CPU check needs them."""
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    X = torch.randn(ns, nd, generator=gen, device=device, dtype=torch.float32)
+    if dtype is not None and dtype != torch.float32:
+        X = X.to(dtype)
+    return X
+
+
 def lanczos_start(nd: int, seed: int) -> np.ndarray:
     """N(0,1) start vector of the spectral-bound Lanczos pass (not normalised)."""
     return _rng(seed, _KEY_LANCZOS).standard_normal(nd)

@@ -362,9 +362,9 @@ def test_large_sampled_columns():
 
 @pytest.mark.parametrize("ns,nd", [(1, 700), (7, 5000), (33, 3089), (64, 5000), (64, 131)])
 def test_rotation_f32_blocks(ns, nd):
-    # FP32 blocks of at most 64 columns take the matrix-core kernel (FP32
-    # accumulation): against the oracle's FP64 product of the same FP32 values,
-    # with padded leading dimension and a ragged tail of points
+    # FP32 blocks (vector kernel, FP32 sums): against the oracle's FP64
+    # product of the same FP32 values, with padded leading dimension and a
+    # ragged tail of points
     binding = _b()
     rng = np.random.default_rng(1000 + ns)
     Y = inputs.round_to_f32(rng.standard_normal((ns, nd)))
@@ -376,3 +376,70 @@ def test_rotation_f32_blocks(ns, nd):
     err = rel_err(R, ref)
     print("FP32 rotation ns", ns, "nd", nd, "max per-column relative error", err)
     assert err <= 2e-6
+
+
+VEC = [
+    # (grid, h, natoms, lmax, ns, radius, m): grids the vector step takes
+    # (z extent a multiple of 4): partial z and y patches, x extents that
+    # are not a multiple of the 8-plane projection segment, fewer x planes
+    # than the stencil radius, radius below 6
+    ((21, 19, 36), 0.45, 3, 2, 3, 6, 6),
+    ((5, 40, 64), 0.5, 2, 1, 2, 6, 4),
+    ((33, 24, 8), 0.6, 1, 1, 4, 4, 5),
+    ((18, 18, 20), 0.5, 2, 2, 1, 6, 7),
+]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("case", VEC, ids=[f"{c[0]}-r{c[5]}-ns{c[4]}" for c in VEC])
+def test_vector_step_edges(case, dtype):
+    """The vector step kernels (16-byte units, fused projector scatter and
+    gather) against the oracle: padded leading dimensions (multiples of the
+    unit), every patch height of the dtype, H X and the filter."""
+    n, h, natoms, lmax, ns, radius, m = case
+    binding = _b()
+    cl = inputs.make_cluster(n, h, natoms, 8, lmax, seed=sum(n) + 1, min_dist=0.0, margin=1.0, radius=radius)
+    rng = np.random.default_rng(sum(n) + ns)
+    X = rng.standard_normal((ns, cl.nd))
+    if dtype == "f32":
+        tdt, code, tol, heights = torch.float32, binding.SPARC_F32, TOL32, (16, 32, 64)
+        X, ocl, pad = inputs.round_to_f32(X), inputs.round_cluster_f32(cl), 4
+    else:
+        tdt, code, tol, heights = torch.float64, binding.SPARC_F64, TOL64, (8, 16, 32)
+        ocl, pad = cl, 2
+    op = binding.Operator(cl)
+    big = torch.zeros((ns, cl.nd + 4 * pad), dtype=tdt, device="cuda")
+    big[:, : cl.nd] = dev(X, tdt)
+    Xv = big[:, : cl.nd]
+    a0, a, b = -3.0, 2.0, oracle.upper_bound(cl)
+    href = oracle.h_apply(ocl, X)
+    fref = oracle.cheb_filter(ocl, X, m, a0, a, b)
+    for ty in heights:
+        op.set_launch(code, 32, ty, 0)
+        assert op.step_config(code, ns)[:2] == (32, ty)
+        outbig = torch.full((ns, cl.nd + 2 * pad), 7.0, dtype=tdt, device="cuda")
+        op.h_apply(Xv, outbig[:, : cl.nd])
+        assert rel_err(host(outbig[:, : cl.nd]), href) <= tol, ty
+        assert torch.all(outbig[:, cl.nd:] == 7.0)  # padding untouched
+        e = rel_err(host(op.cheb_filter(Xv, m, a0, a, b)), fref)
+        print(f"{n} {dtype} TY={ty} filter err {e:.2e}")
+        assert e <= tol, ty
+
+
+def test_crowded_patches_fall_back():
+    """More projector cubes on one patch than the vector kernels keep: the
+    library takes a lower patch (or the scalar kernels), with the same
+    results as the oracle."""
+    binding = _b()
+    cl = inputs.make_cluster((12, 40, 32), 0.5, 36, 4, 1, seed=9, min_dist=0.0, margin=1.0)
+    rng = np.random.default_rng(9)
+    X = rng.standard_normal((2, cl.nd))
+    op = binding.Operator(cl)
+    print("crowded: patch f32", op.step_config(binding.SPARC_F32, 2), "f64", op.step_config(binding.SPARC_F64, 2))
+    a0, a, b = -3.0, 2.0, oracle.upper_bound(cl)
+    assert rel_err(host(op.h_apply(dev(X))), oracle.h_apply(cl, X)) <= TOL64
+    assert rel_err(host(op.cheb_filter(dev(X), 6, a0, a, b)), oracle.cheb_filter(cl, X, 6, a0, a, b)) <= TOL64
+    X32 = inputs.round_to_f32(X)
+    ocl = inputs.round_cluster_f32(cl)
+    got = host(op.cheb_filter(dev(X32, torch.float32), 6, a0, a, b))
+    assert rel_err(got, oracle.cheb_filter(ocl, X32, 6, a0, a, b)) <= TOL32
