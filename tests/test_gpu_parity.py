@@ -334,30 +334,77 @@ def test_lanczos_long_run_stays_orthogonal(n, k):
     assert np.abs(alpha - ra).max() <= 1e-8 and np.abs(beta - rb).max() <= 1e-8
 
 
-def test_large_sampled_columns():
-    """Largest single-GPU workload (160^3 grid, 128 atoms with 9 projectors
-    each, 600 orbitals, degree 30) in FP32: three sampled columns against the
-    FP64 oracle fed the same FP32-rounded inputs, and column independence at
-    full size."""
+@pytest.fixture(scope="module")
+def large():
     c = inputs.LARGE
-    cl = inputs.case_cluster(c.name)
+    return c, inputs.case_cluster(c.name)
+
+
+def test_large_workload_pass(large):
+    """The largest single-GPU workload (160^3 grid, h = 0.35, 128 atoms with 9
+    projectors each, 600 orbitals, m = 30), the configuration the benchmark
+    times: device Lanczos against the oracle's, FP64 and FP32 filters on
+    sampled columns against the oracle, FP64 Rayleigh-Ritz of both blocks
+    (the FP32 filter's Ritz values against the FP64 filter's), and the
+    rotation: Ritz pairs through the oracle's H (Rayleigh quotients,
+    orthonormality) and sampled rows of Y Q."""
+    c, cl = large
+    binding = _b()
+    op = binding.Operator(cl)
+    v0 = inputs.lanczos_start(cl.nd, c.seed)
+    _, _, theta = op.lanczos(40, dev(v0))
+    _, _, rt = oracle.lanczos(cl, 40, v0)
+    print("large lanczos max |dtheta| %.2e" % np.abs(theta - rt).max())
+    assert np.abs(theta - rt).max() <= TOL_RITZ
+    a0, a, b = binding.select_bounds(theta, 8, ubound=op.upper_bound())
+    oa0, oa, ob = oracle.select_bounds(rt, 8, ubound=oracle.upper_bound(cl))
+    assert max(abs(a0 - oa0), abs(a - oa), abs(b - ob)) <= TOL_RITZ
+
     cols = [0, 299, 599]
-    a0, a, b = -5.0, 3.0, oracle.upper_bound(cl)
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(c.seed)
-    X = torch.randn(c.ns, cl.nd, generator=gen, device="cuda", dtype=torch.float32)
-    Xs = inputs.round_to_f32(inputs.orbitals(cl.nd, c.ns, c.seed, cols=cols))
-    X[cols] = dev(Xs, torch.float32)
-    op = _b().Operator(cl)
-    Y = op.cheb_filter(X, c.m, a0, a, b)
-    got = host(Y[cols])
-    del Y
-    ref = oracle.cheb_filter(inputs.round_cluster_f32(cl), Xs, c.m, a0, a, b)
-    e32 = rel_err(got, ref)
-    print("large sampled error f32 %.3e" % e32)
-    assert e32 <= TOL32
-    one = host(op.cheb_filter(X[cols[1]:cols[1] + 1].contiguous(), c.m, a0, a, b))
-    assert np.array_equal(one[0], got[1])
+    X32 = inputs.device_orbitals(cl.nd, c.ns, c.seed)
+    Xs = X32[cols].double().cpu().numpy()
+    # FP64 filter, sampled columns
+    Y64 = op.cheb_filter(X32.double(), c.m, a0, a, b)
+    e64 = rel_err(host(Y64[cols]), oracle.cheb_filter(cl, Xs, c.m, a0, a, b))
+    # FP32 filter, sampled columns against the oracle on the FP32-rounded inputs
+    Y32 = op.cheb_filter(X32, c.m, a0, a, b)
+    e32 = rel_err(host(Y32[cols]), oracle.cheb_filter(inputs.round_cluster_f32(cl), Xs, c.m, a0, a, b))
+    print("large filter errors f64 %.2e f32 %.2e" % (e64, e32))
+    assert e64 <= TOL64 and e32 <= TOL32
+    # column independence at full size: a column filtered alone is bit-identical
+    one = op.cheb_filter(X32[cols[1]:cols[1] + 1].contiguous(), c.m, a0, a, b)
+    torch.cuda.synchronize()
+    assert torch.equal(one[0], Y32[cols[1]])
+    del X32, one
+
+    # FP64 Rayleigh-Ritz on both filtered blocks
+    th32, _ = op.rayleigh_ritz(Y32, want_vectors=False)
+    del Y32
+    torch.cuda.empty_cache()
+    th64, Qt = op.rayleigh_ritz(Y64)
+    d = np.abs(th32 - th64).max()
+    print("large Ritz values, FP32 filter vs FP64 filter: max |d| %.2e Ha" % d)
+    assert d <= TOL_RITZ
+    # rotation of the FP64 block; Ritz pairs checked with the oracle's H
+    R = binding.rotate(Y64, Qt)
+    pick = [0, 1, 300, 599]
+    Rp = host(R[pick])
+    HR = oracle.h_apply(cl, Rp)
+    rq = np.einsum("ij,ij->i", Rp, HR) / np.einsum("ij,ij->i", Rp, Rp)
+    print("large Rayleigh quotients vs Ritz values: max |d| %.2e" % np.abs(rq - th64[pick]).max())
+    assert np.abs(rq - th64[pick]).max() <= TOL_RITZ
+    gram = Rp @ Rp.T
+    assert np.abs(gram - np.eye(len(pick))).max() < 1e-9
+    # sampled grid rows of R = Y Q against the product on the host
+    rows = np.random.default_rng(3).choice(cl.nd, 48, replace=False)
+    idx = torch.from_numpy(rows).cuda()
+    Yr = Y64[:, idx].cpu().numpy()              # (ns, rows)
+    Q = Qt.cpu().numpy().T                       # column-major Q as returned
+    ref = Q.T @ Yr                               # row c of R at the sampled rows
+    got = R[:, idx].cpu().numpy()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print("large rotation sampled rows rel err %.2e" % err)
+    assert err <= 1e-12
 
 
 @pytest.mark.parametrize("ns,nd", [(1, 700), (7, 5000), (33, 3089), (64, 5000), (64, 131)])
