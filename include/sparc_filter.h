@@ -122,6 +122,25 @@ size_t sparc_workspace_bytes(const sparc_op *op, int32_t dtype, int32_t ns, int3
 int sparc_h_apply(const sparc_op *op, int32_t dtype, const void *X, int64_t ldx, void *Y, int64_t ldy,
                   int32_t ns, void *ws, size_t ws_bytes, void *stream);
 
+/* Y = H X as sparc_h_apply, without allocation and without a workspace
+ * argument: for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * projector gather partials live in a fixed device array of
+ * sparc_noalloc_scratch_bytes() bytes (16 MiB) that every GPU the library
+ * runs on holds until the process ends; the first call on a device looks up
+ * its address.  Calls that need more (8 * nproj_total * ns * element size,
+ * i.e. nproj_total * ns up to 262144 in FP64 or 524288 in FP32) fail with
+ * SPARC_E_WORKSPACE.  Nothing in the array needs clearing between calls.
+ * All calls on one GPU share the array: calls that overlap in time on one
+ * GPU (on different streams or threads) race and must not be made.  Results
+ * are bitwise those of sparc_h_apply.  Asynchronous.
+ * Errors: as sparc_h_apply, SPARC_E_WORKSPACE (scratch too small). */
+int sparc_h_apply_noalloc(const sparc_op *op, int32_t dtype, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                          int32_t ns, void *stream);
+
+/* Size in bytes of the fixed scratch array of sparc_h_apply_noalloc. */
+size_t sparc_noalloc_scratch_bytes(void);
+
 /* Chebyshev filter of degree m (Sec. 3.4, Eq. ChebFilter and Alg. 2) in the
  * scaled three-term form of the filtered subspace iteration the paper cites:
  *   e = (b - a)/2, c = (b + a)/2, sigma_1 = e/(a0 - c), tau = 2/sigma_1,

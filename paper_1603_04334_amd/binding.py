@@ -104,6 +104,8 @@ _SIGS = {
     "sparc_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "sparc_cleared_hip_errors": (_i64, []),
     "sparc_stream_copy": (_i32, [_vp, _vp, _sz, _vp]),
+    "sparc_h_apply_noalloc": (_i32, [_vp, _i32, _vp, _i64, _vp, _i64, _i32, _vp]),
+    "sparc_noalloc_scratch_bytes": (_sz, []),
     "sparc_last_error": (ctypes.c_char_p, []),
     "sparc_profile_enable": (_i32, [_i32]),
     "sparc_profile_read": (_i32, [_i32, ctypes.POINTER(_i64), _dp]),
