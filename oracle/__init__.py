@@ -21,6 +21,10 @@ Functions and the passages they follow:
 * ``rayleigh_ritz``     Sec. 3.4 Eq. SubspaceGeneralizedEigenproblem and the
                         H_s, M_s definitions that follow it.
 * ``rotate``            Sec. 3.4 Eq. OrbitalTransformation.
+* ``fermi_level``       Sec. 3.4 Eq. FermiEnergyConstraintFormulation (the
+                        occupation constraint 2 sum_n g_n = N_e) and the
+                        occupations g_n; Sec. 4 (k_B T = 1e-3 Ha).
+* ``density``           Sec. 3.4, the electron density rho = (2/h^3) sum_n g_n psi_n^2.
 * ``dense_hamiltonian`` brute-force N_d x N_d matrix for tiny grids.
 * ``cheb_closed_form``  C_m(x) from its trigonometric/hyperbolic definition.
 """
@@ -267,6 +271,76 @@ def rayleigh_ritz(cluster, Y: np.ndarray, bc: int = 0):
 def rotate(Y: np.ndarray, vec: np.ndarray) -> np.ndarray:
     """Psi = Psi_f Q with Psi_f column-major (rows of Y are columns of Psi_f)."""
     return (np.asarray(Y, dtype=np.float64).T @ vec).T.copy()
+
+
+# ----------------------------------------------------------------------------- occupations and density
+
+KT_DEFAULT = 1e-3  # smearing k_B T of the paper's runs (Sec. 4), Hartree
+
+
+def occupations(theta, lambda_f: float, kT: float = KT_DEFAULT) -> np.ndarray:
+    """g_n = 1 / (1 + exp((theta_n - lambda_f) / kT)) (Sec. 3.4), evaluated as
+    exp(-x)/(1 + exp(-x)) for x > 0 so that no exponential overflows."""
+    x = (np.asarray(theta, dtype=np.float64) - float(lambda_f)) / float(kT)
+    out = np.empty_like(x)
+    pos = x > 0
+    e = np.exp(-x[pos])
+    out[pos] = e / (1.0 + e)
+    out[~pos] = 1.0 / (1.0 + np.exp(x[~pos]))
+    return out
+
+
+def fermi_level(theta, ne: float, kT: float = KT_DEFAULT) -> float:
+    """The Fermi energy lambda_f: the root of 2 sum_n g_n(lambda_f) = N_e
+    (Sec. 3.4 Eq. FermiEnergyConstraintFormulation).  The left side increases
+    strictly with lambda_f from 0 to 2 N_s, so for 0 < N_e < 2 N_s the root is
+    unique; it is bracketed 50 k_B T beyond the extreme eigenvalues and found
+    by bisection until the bracket stops shrinking (the paper uses Brent's
+    method, Sec. 4, which converges to the same root).
+
+    The constraint is evaluated as 2 ((#{theta_n <= l} - N_e / 2)
+    + sum_{theta_n > l} g_n - sum_{theta_n <= l} (1 - g_n)), with 1 - g_n = g_n(2 l - theta_n)
+    by the symmetry of the Fermi-Dirac function: the same value as
+    2 sum_n g_n - N_e, but without the cancellation of 1 - g_n, so that the
+    root stays determined across gaps up to about 1400 k_B T (beyond that the
+    tails underflow and every point of the gap satisfies the constraint)."""
+    th = np.asarray(theta, dtype=np.float64)
+    ns = th.size
+    if not 0.0 < ne < 2.0 * ns:
+        raise ValueError("need 0 < N_e < 2 N_s")
+
+    def f(lf):
+        below = th <= lf
+        tails = occupations(th[~below], lf, kT).sum() - occupations(2.0 * lf - th[below], lf, kT).sum()
+        # the integer part first, so that tails below its rounding unit survive
+        return 2.0 * ((below.sum() - 0.5 * ne) + tails)
+    lo, hi = th.min() - 50.0 * kT, th.max() + 50.0 * kT
+    while f(lo) > 0:
+        lo -= 50.0 * kT
+    while f(hi) < 0:
+        hi += 50.0 * kT
+    for _ in range(400):
+        mid = 0.5 * (lo + hi)
+        if mid <= lo or mid >= hi:
+            break
+        if f(mid) < 0:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def density(Psi: np.ndarray, g, h: float) -> np.ndarray:
+    """rho(x) = (2/h^3) sum_n g_n psi_n(x)^2 (Sec. 3.4) for an orbital block
+    (ns, nd) whose rows are the orbitals."""
+    Psi = np.asarray(Psi, dtype=np.float64)
+    if Psi.ndim == 1:
+        Psi = Psi.reshape(1, -1)
+    g = np.asarray(g, dtype=np.float64)
+    rho = np.zeros(Psi.shape[1])
+    for n in range(Psi.shape[0]):
+        rho += g[n] * Psi[n] * Psi[n]
+    return 2.0 / h ** 3 * rho
 
 
 # ----------------------------------------------------------------------------- closed forms, brute force
