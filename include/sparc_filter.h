@@ -223,6 +223,32 @@ size_t sparc_rotate_workspace_bytes(int32_t dtype, int32_t ns);
 int sparc_rotate(int32_t dtype, const void *Y, int64_t ldy, int64_t nd, int32_t ns, const double *Q,
                  void *out, int64_t ldo, void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------- occupations and density */
+
+/* Fermi energy (Sec. 3.4, Eq. FermiEnergyConstraintFormulation): the root
+ * lambda_f of 2 sum_n g_n = N_e with g_n = 1 / (1 + exp((theta_n -
+ * lambda_f) / kT)), found by Brent's method as in Sec. 4 (the paper's runs
+ * use kT = 1e-3 Ha).  theta: host array of ns eigenvalues (any order); ne:
+ * electron count, 0 < ne < 2 ns; kT > 0 in the units of theta.  lambda_f
+ * receives the root, to about 1e-15 relative; occ, when not null, a host
+ * array of ns occupations g_n.  The residual is evaluated without
+ * cancellation, so the root is determined across gaps of up to about 1400 kT;
+ * wider gaps leave a flat residual and any point of the gap is returned.
+ * Errors: SPARC_E_ARG (null pointers, ns < 1, ne outside (0, 2 ns), kT <= 0,
+ * non-finite theta), SPARC_E_BOUNDS (no bracket found).  Host only. */
+int sparc_fermi_level(const double *theta, int32_t ns, double ne, double kT, double *lambda_f, double *occ);
+
+/* Electron density on the grid (Sec. 3.4): rho[i] = (2/h^3) sum_n occ[n]
+ * psi_n[i]^2 for the nd x ns block psi (column n = orbital n at psi + n ld,
+ * dtype SPARC_F64 or SPARC_F32), occ a device FP64 array of ns occupations,
+ * rho a device FP64 array of nd values (overwritten).  Products and sums run
+ * in FP64, columns in ascending order, so the result is independent of the
+ * launch.  One pass over psi: s nd ns bytes read, 8 nd written.  rho must not
+ * overlap psi.  Asynchronous on stream.  Errors: SPARC_E_ARG, SPARC_E_SHAPE
+ * (nd < 1, ld < nd, h <= 0), SPARC_E_ALIAS, SPARC_E_HIP. */
+int sparc_density(int32_t dtype, const void *psi, int64_t ld, int64_t nd, int32_t ns, const double *occ, double h,
+                  double *rho, void *stream);
+
 /* ------------------------------------------------------- batched filters */
 
 /* One filter of a batch: the arguments of sparc_cheb_filter for one cluster.
@@ -400,7 +426,9 @@ int64_t sparc_cleared_hip_errors(void);
 /* Per-kernel timing with HIP events recorded around each launch on the
  * launching stream.  kernel: 0 = fused stencil/potential/recurrence step
  * with Y_{k-1} (k >= 1), 1 = projector gather, 2 = projector scatter, 3 = the
- * same fused step without Y_{k-1} (first filter step, H application).  enable(1) starts recording;
+ * same fused step without Y_{k-1} (first filter step, H application), 4 =
+ * the density pass, 5 = the nonlocal-force reduction, 6 = the Poisson
+ * operator, 7 unused.  enable(1) starts recording;
  * read() synchronises the recorded events and returns the number of launches
  * and their summed duration in ms; reset() clears the counts. */
 int sparc_profile_enable(int32_t on);

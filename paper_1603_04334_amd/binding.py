@@ -104,6 +104,8 @@ _SIGS = {
     "sparc_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "sparc_cleared_hip_errors": (_i64, []),
     "sparc_stream_copy": (_i32, [_vp, _vp, _sz, _vp]),
+    "sparc_fermi_level": (_i32, [_dp, _i32, _dbl, _dbl, _dp, _dp]),
+    "sparc_density": (_i32, [_i32, _vp, _i64, _i64, _i32, _vp, _dbl, _vp, _vp]),
     "sparc_h_apply_noalloc": (_i32, [_vp, _i32, _vp, _i64, _vp, _i64, _i32, _vp]),
     "sparc_noalloc_scratch_bytes": (_sz, []),
     "sparc_last_error": (ctypes.c_char_p, []),
@@ -337,6 +339,33 @@ def select_bounds(theta, nwant: int = 8, shift: float = 0.1, bfactor: float = 1.
                                     float(ubound), ctypes.byref(a0), ctypes.byref(a), ctypes.byref(b)),
           "sparc_select_bounds")
     return a0.value, a.value, b.value
+
+
+def fermi_level(theta, ne: float, kT: float = 1e-3):
+    """(lambda_f, occupations) for host eigenvalues theta and N_e electrons."""
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+    occ = np.empty_like(th)
+    lf = ctypes.c_double()
+    check(lib().sparc_fermi_level(th.ctypes.data_as(_dp), len(th), float(ne), float(kT), ctypes.byref(lf),
+                                  occ.ctypes.data_as(_dp)), "sparc_fermi_level")
+    return lf.value, occ
+
+
+def density(Psi, occ, h: float, rho=None, stream=None):
+    """rho = (2/h^3) sum_n occ[n] Psi[n]^2 for an (ns, nd) device block;
+    occ: device FP64 (ns,), rho: device FP64 (nd,) (allocated if None)."""
+    import torch
+    ns, nd = Psi.shape[0], Psi.shape[1]
+    ld = _block(Psi, nd, "Psi")[1]
+    if occ.dtype != torch.float64 or occ.numel() != ns or not occ.is_cuda or not occ.is_contiguous():
+        raise ValueError("occ must be a contiguous device float64 tensor of ns entries")
+    if rho is None:
+        rho = torch.empty(nd, dtype=torch.float64, device=Psi.device)
+    if rho.dtype != torch.float64 or rho.numel() != nd or not rho.is_contiguous():
+        raise ValueError("rho must be a contiguous float64 tensor of nd entries")
+    check(lib().sparc_density(_dtype_code(Psi), _ptr(Psi), ld, nd, ns, _ptr(occ), float(h), _ptr(rho),
+                              _stream(stream)), "sparc_density")
+    return rho
 
 
 def rotate(Y, Qt, out=None, ws=None, stream=None):

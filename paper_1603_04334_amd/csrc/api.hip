@@ -31,8 +31,9 @@ struct ProfRec {
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRec> g_prof_pending;
-int64_t g_prof_count[4] = {0, 0, 0, 0};
-double g_prof_ms[4] = {0, 0, 0, 0};
+constexpr int kProfKernels = 8;
+int64_t g_prof_count[kProfKernels] = {};
+double g_prof_ms[kProfKernels] = {};
 }  // namespace
 
 ProfScope::ProfScope(int k, hipStream_t s) : kernel(k), stream(s)
@@ -155,7 +156,7 @@ int sparc_profile_reset(void)
         (void)hipEventDestroy(r.b);
     }
     g_prof_pending.clear();
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < kProfKernels; ++k) {
         g_prof_count[k] = 0;
         g_prof_ms[k] = 0;
     }
@@ -164,7 +165,7 @@ int sparc_profile_reset(void)
 
 int sparc_profile_read(int32_t kernel, int64_t *launches, double *total_ms)
 {
-    if (kernel < 0 || kernel > 3) return fail(SPARC_E_ARG, "kernel id must be 0..3");
+    if (kernel < 0 || kernel >= kProfKernels) return fail(SPARC_E_ARG, "kernel id must be 0..7");
     std::lock_guard<std::mutex> lk(g_prof_mu);
     for (auto &r : g_prof_pending) {
         if (hipEventSynchronize(r.b) != hipSuccess) return fail(SPARC_E_HIP, "event synchronisation failed");

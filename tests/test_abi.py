@@ -61,3 +61,31 @@ def test_invalid_grids_rejected_without_device():
         g.h, g.radius = hh, r
         assert lib.sparc_op_create(ctypes.byref(g), veff, 0, None, ctypes.byref(h)) == binding.SPARC_E_SHAPE
         assert not h.value
+
+
+def test_host_fermi_level_against_oracle():
+    """The library's Brent solve of the electron-count constraint (host only)
+    against the oracle's bisection, on random spectra, a degenerate level, a
+    gapped spectrum, and the argument checks."""
+    import numpy as np
+
+    import oracle
+    _lib_or_skip()
+    rng = np.random.default_rng(11)
+    for ns, ne, kT in ((60, 37.0, 1e-3), (630, 1200.0, 1e-3), (8, 3.5, 5e-2), (300, 1.0, 1e-3), (300, 599.0, 1e-3)):
+        th = rng.permutation(np.sort(rng.uniform(-3.0, 1.0, ns)))  # any order
+        lf, occ = binding.fermi_level(th, ne, kT)
+        lref = oracle.fermi_level(th, ne, kT)
+        assert abs(lf - lref) <= 1e-12 * max(1.0, abs(lref))
+        assert np.allclose(occ, oracle.occupations(th, lref, kT), rtol=1e-9, atol=1e-15)
+        assert abs(2.0 * occ.sum() - ne) < 1e-9 * ne
+    # degenerate: l_f = e - kT ln(2 ns / ne - 1)
+    lf, _ = binding.fermi_level([-0.8] * 40, 17.0, 1e-3)
+    assert abs(lf - (-0.8 - 1e-3 * np.log(80.0 / 17.0 - 1.0))) < 1e-12
+    # gap of 0.65 Ha with the filled/empty split at 6 electrons: the midpoint
+    lf, occ = binding.fermi_level([-1.0, -0.9, -0.85, -0.2, -0.1, 0.4], 6.0, 1e-3)
+    assert abs(lf - (-0.525)) < 1e-12 and np.all(occ[:3] == 1.0) and np.all(occ[3:] < 1e-100)
+    for args in (([0.0, 1.0], 4.0, 1e-3), ([0.0, 1.0], 0.0, 1e-3), ([0.0, 1.0], 1.0, 0.0), ([0.0, np.nan], 1.0, 1e-3)):
+        with pytest.raises(binding.SparcError) as ei:
+            binding.fermi_level(*args)
+        assert ei.value.status == binding.SPARC_E_ARG
