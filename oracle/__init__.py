@@ -25,6 +25,9 @@ Functions and the passages they follow:
                         occupation constraint 2 sum_n g_n = N_e) and the
                         occupations g_n; Sec. 4 (k_B T = 1e-3 Ha).
 * ``density``           Sec. 3.4, the electron density rho = (2/h^3) sum_n g_n psi_n^2.
+* ``chefsi_passes``     Sec. 3.4 last paragraph and Sec. 4: repeated CheFSI
+                        passes (filter, Rayleigh-Ritz, Fermi level, rotation)
+                        with the cutoff set to the previous Fermi level + 0.1 Ha.
 * ``dense_hamiltonian`` brute-force N_d x N_d matrix for tiny grids.
 * ``cheb_closed_form``  C_m(x) from its trigonometric/hyperbolic definition.
 """
@@ -341,6 +344,38 @@ def density(Psi: np.ndarray, g, h: float) -> np.ndarray:
     for n in range(Psi.shape[0]):
         rho += g[n] * Psi[n] * Psi[n]
     return 2.0 / h ** 3 * rho
+
+
+# ----------------------------------------------------------------------------- CheFSI passes
+
+CUTOFF_SHIFT = 0.1  # lambda_c = previous Fermi energy + 0.1 Ha (Sec. 4)
+
+
+def chefsi_passes(cluster, X: np.ndarray, m, passes: int, ne: float, a0: float, a: float, b: float,
+                  kT: float = KT_DEFAULT, shift: float = CUTOFF_SHIFT, bc: int = 0):
+    """``passes`` CheFSI steps on the orbital block X (Sec. 3.4): filter with
+    bounds (a0, cutoff, b), Rayleigh-Ritz, Fermi level of the Ritz values,
+    rotation.  The first pass uses the cutoff ``a``; each later pass the
+    previous pass's Fermi level plus ``shift`` (Sec. 4).  a0 and b (lambda_1
+    and lambda_Nd of Alg. 2) stay fixed: without a density update H does not
+    change between the passes of the first SCF iteration (Sec. 3.4, last
+    paragraph).  m: one degree for every pass, or a sequence of per-pass
+    degrees.  Returns (rotated block, list of per-pass dicts with the cutoff,
+    degree, Ritz values and Fermi level)."""
+    degrees = [int(m)] * passes if np.isscalar(m) else [int(d) for d in m]
+    if len(degrees) != passes:
+        raise ValueError("one degree per pass")
+    X = _block(X, cluster.nd)
+    cutoff = float(a)
+    record = []
+    for p in range(passes):
+        Y = cheb_filter(cluster, X, degrees[p], a0, cutoff, b, bc=bc)
+        theta, vec, _, _ = rayleigh_ritz(cluster, Y, bc)
+        lf = fermi_level(theta, ne, kT)
+        X = rotate(Y, vec)
+        record.append(dict(cutoff=cutoff, degree=degrees[p], theta=theta, lambda_f=lf))
+        cutoff = lf + shift
+    return X, record
 
 
 # ----------------------------------------------------------------------------- closed forms, brute force
