@@ -290,7 +290,10 @@ class ServeSetup:
             cl = inputs.make_cluster(c["n"], c["h"], c["natoms"], c["zmax"], c["lmax"], sd)
             src = self.X32 if c["fp32"] else self.X64
             X0 = src[: cl.nd * c["ns"]].view(c["ns"], cl.nd)
-            self.descs[sd] = binding.cluster_desc(cl, X0, self.v0[: cl.nd], c["m"])
+            # electrons of the cluster's atoms; where the 256-orbital cap cuts
+            # ns below N_e/2 + 30, the count the capped block is sized for
+            ne = min(c["ne"], 2 * (c["ns"] - 30))
+            self.descs[sd] = binding.cluster_desc(cl, X0, self.v0[: cl.nd], c["m"], ne=ne)
 
 
 def serve_point(setup, rate, nclusters, workers):
@@ -360,7 +363,9 @@ def serve_point(setup, rate, nclusters, workers):
             "p50_ms_f64": q(lat[~is32], 50), "p99_ms_f64": q(lat[~is32], 99),
             "session_p50_ms": q(sess, 50), "session_p99_ms": q(sess, 99),
             "throughput_req_s": len(ok) / span, "updates_per_s": upd / span, "span_s": span,
-            "max_arrival_lag_ms": lag * 1e3, "host_cluster_records_left": records[0]}
+            "max_arrival_lag_ms": lag * 1e3, "host_cluster_records_left": records[0],
+            "passes": int(sum(r["passes"] for _, _, r in ok)),
+            "degree_halvings": int(sum(r["halvings"] for _, _, r in ok))}
 
 
 def serve_measure(rates, nrequests, workers):
@@ -374,9 +379,10 @@ def serve_measure(rates, nrequests, workers):
     for r in rates:
         points.append(serve_point(setup, r, nclusters, workers))
         print(f"serving point done: {json.dumps(points[-1])}", file=sys.stderr, flush=True)
-    out = {"workload": f"{nclusters} cluster sessions x {SERVE_STEPS} filtered-subspace passes (Lanczos bounds on "
-                       f"the first), grid edge log-uniform 24-128, h=0.45, 1-64 atoms, N_s = N_e/2+30, degree 20-30, "
-                       f"FP32:FP64 = 80:20, Poisson session arrivals at rate/{SERVE_STEPS}, passes chained",
+    out = {"workload": f"{nclusters} cluster sessions x {SERVE_STEPS} SCF-iteration requests (the first: Lanczos "
+                       f"bounds and 3 CheFSI passes from a random block; later: one pass, cutoff = last Fermi level "
+                       f"+ 0.1 Ha), grid edge log-uniform 24-128, h=0.45, 1-64 atoms, N_s = N_e/2+30, degree 20-30, "
+                       f"FP32:FP64 = 80:20, Poisson session arrivals at rate/{SERVE_STEPS}, requests chained",
            "workers": workers, "budget_bytes": SERVE_BUDGET, "points": points,
            "cleared_hip_errors": int(binding.lib().sparc_cleared_hip_errors())}
     del setup

@@ -30,6 +30,8 @@
 
 namespace sparc {
 
+thread_local bool g_rr_rank_deficient = false;  // set by the last Rayleigh-Ritz call of this thread
+
 constexpr int kRedBlocks = 1024;  // blocks of the first reduction pass: one partial per block
 constexpr int kDotGroup = 8;      // vectors per pass over a block's segment
 constexpr int kUnroll = 4;        // points per thread with loads in flight together
@@ -852,6 +854,7 @@ size_t sparc_rr_workspace_bytes(const sparc_op *op, int32_t dtype, int32_t ns)
 int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_t ldy, int32_t ns, double *theta,
                         double *evec, void *ws, size_t ws_bytes, void *stream)
 {
+    g_rr_rank_deficient = false;
     if (!op || !Y || !theta) return fail(SPARC_E_ARG, "null argument");
     if (dtype != SPARC_F64 && dtype != SPARC_F32) return fail(SPARC_E_ARG, "bad dtype");
     if (ns < 1 || ldy < op->nd) return fail(SPARC_E_SHAPE, "ns < 1 or ldy < N_d");
@@ -931,7 +934,13 @@ int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_
     if (hinfo != 0) {
         if (ns <= 64 && hinfo == ns + 1)
             return fail(SPARC_E_BREAKDOWN, "Jacobi eigensolver did not converge within its sweep limit");
-        return fail(SPARC_E_BREAKDOWN, "generalized eigensolver failed (info=" + std::to_string(hinfo) +
+        if (ns > 64 && hinfo <= ns)
+            return fail(SPARC_E_BREAKDOWN, "rocsolver_dsygvd: the tridiagonal eigensolver did not converge (info=" +
+                                               std::to_string(hinfo) + ")");
+        // the Cholesky factorisation of M_s failed (small solver: info = the
+        // failing column; rocSOLVER: info = ns + that column)
+        g_rr_rank_deficient = true;
+        return fail(SPARC_E_BREAKDOWN, "Cholesky of M_s failed (info=" + std::to_string(hinfo) +
                                            "): the filtered block is numerically rank deficient");
     }
     return SPARC_OK;

@@ -1,21 +1,20 @@
-// Request server for filtered-subspace steps (Sec. 3.4) on resident clusters.
+// Request server for CheFSI passes (Sec. 3.4) on resident clusters.
 //
-// A request asks for one filtered-subspace pass on a cluster: on the
+// A request asks for one SCF iteration's eigensolve on a cluster.  On the
 // cluster's first request its operator is built, its orbitals are copied into
-// a resident block and the filter bounds come from the device Lanczos (Sec. 4);
-// every request then runs the Chebyshev filter, the FP64 Rayleigh-Ritz step
-// and the rotation, leaving the rotated orbitals resident for the cluster's
-// next request (the later passes of one SCF iteration sequence, Sec. 3.4 last
-// paragraph).  The first pass of an FP32 cluster runs in FP64: filtering an
-// unconverged block pulls every column towards the lowest eigenvectors, and
-// the remaining directions can fall below FP32 resolution, leaving M_s
-// singular; from the second pass on the columns are Ritz vectors, each
-// filtered with its own gain, and FP32 keeps them apart.  Requests of one cluster run in submission order; requests of
-// different clusters run concurrently on the workers' own streams, so work
-// admitted while other requests are on the device overlaps with them
-// (continuous batching).  A cluster is admitted only when its device
-// footprint fits the budget next to the resident clusters; its memory is
-// returned after the request that carries `release`.  Every step is
+// a resident block, the filter bounds come from the device Lanczos (Sec. 4)
+// and the first-SCF rule runs: several CheFSI passes (filter, FP64
+// Rayleigh-Ritz, Fermi level, rotation) from the caller's random block
+// without a density update in between (Sec. 3.4, last paragraph).  Every
+// later request runs one pass on the resident rotated orbitals.  The cutoff
+// of each pass after the first is the previous pass's Fermi level + 0.1 Ha
+// (Sec. 4), carried from request to request.  Every pass runs in the
+// cluster's own dtype.  Requests of one cluster run in submission order;
+// requests of different clusters run concurrently on the workers' own
+// streams, so work admitted while other requests are on the device overlaps
+// with them (continuous batching).  A cluster is admitted only when its
+// device footprint fits the budget next to the resident clusters; its memory
+// is returned after the request that carries `release`.  Every step is
 // deterministic and per-cluster buffers are private, so a cluster's results
 // do not depend on what else runs.
 #include <chrono>
@@ -51,6 +50,7 @@ struct Cluster {
     std::vector<double> veff;
     std::vector<AtomCopy> atoms;
     int dtype = 0, ns = 0, m = 0;
+    double ne = 0, lambda_f = 0;  // electron count; Fermi level of the last pass
     const void *X0 = nullptr;
     int64_t ldx0 = 0;
     const double *v0 = nullptr;
@@ -84,6 +84,8 @@ struct sparc_server {
     int device = 0;
     size_t budget = 0;
     int lanczos_k = 40;
+    int first_passes = 3;
+    double kT = 1e-3;
     std::mutex mu;
     std::condition_variable cv;
     bool stop = false;
@@ -136,10 +138,8 @@ size_t estimate_footprint(const Cluster &c, int lanczos_k)
     f += 3 * nd * ns * s + 4 * std::max<size_t>(1, nproj) * ns * s;  // X, Y, filter workspace
     f += nd * ns * 8;                                                 // Rayleigh-Ritz H Y
     f += 4 * std::max<size_t>(1, nproj) * ns * 8 + 1024 * 2 * ns * ns * 8 + 4 * (ns + 64) * (ns + 64) * 8 + 4096;
-    // first request only: Lanczos, and for FP32 the FP64 blocks of the first pass
-    size_t first = nd * (lanczos_k + 1) * 8 + 4096 * (lanczos_k + 2) * 8;
-    if (c.dtype == SPARC_F32) first = std::max(first, 3 * nd * ns * 8 + 4 * std::max<size_t>(1, nproj) * ns * 8);
-    return f + first;
+    // first request only: the Lanczos basis and workspace
+    return f + nd * (lanczos_k + 1) * 8 + 4096 * (lanczos_k + 2) * 8;
 }
 
 // Cluster blocks come from the stream-ordered allocator on the worker's
@@ -157,60 +157,27 @@ void free_device(Cluster &c, hipStream_t s)
     c.resident = false;
 }
 
-// one filtered-subspace pass on stream s: Y = p_m(H) X, Rayleigh-Ritz on Y,
-// X = Y Q; theta receives the Ritz values
-int run_pass(Cluster &c, int dtype, void *X, void *Y, void *ws, size_t ws_bytes, hipStream_t s,
-             std::vector<double> &theta)
-{
-    int st;
-    if ((st = sparc_cheb_filter(c.op, dtype, X, c.nd, Y, c.nd, c.ns, c.m, c.a0, c.a, c.b, ws, ws_bytes, s)))
-        return st;
-    if ((st = sparc_rayleigh_ritz(c.op, dtype, Y, c.nd, c.ns, theta.data(), (double *)c.evec, c.rr, c.rr_bytes, s)))
-        return st;
-    return sparc_rotate(dtype, Y, c.nd, c.nd, c.ns, (const double *)c.evec, X, c.nd, c.rot, c.rot_bytes, s);
-}
-
-// first pass of an FP32 cluster, in FP64 from the caller's block; the rotated
-// orbitals are rounded into the resident FP32 block
-int first_pass_f64(Cluster &c, hipStream_t s, std::vector<double> &theta)
-{
-    const size_t blk = (size_t)c.nd * c.ns * sizeof(double);
-    const size_t wb = sparc_workspace_bytes(c.op, SPARC_F64, c.ns, 1);
-    void *x = nullptr, *y = nullptr, *w = nullptr;
-    int st = SPARC_OK;
-    if (hipMallocAsync(&x, blk, s) != hipSuccess || hipMallocAsync(&y, blk, s) != hipSuccess ||
-        hipMallocAsync(&w, wb, s) != hipSuccess)
-        st = fail(SPARC_E_NOMEM, "allocation of the FP64 first-pass blocks failed");
-    if (!st) st = launch_copy<float, double>(c.X0, c.ldx0, x, c.nd, c.nd, c.ns, s);
-    if (!st) st = run_pass(c, SPARC_F64, x, y, w, wb, s, theta);
-    if (!st) st = launch_copy<double, float>(x, c.nd, c.X, c.nd, c.nd, c.ns, s);
-    for (void *p : {x, y, w})
-        if (p) (void)hipFreeAsync(p, s);
-    return st;
-}
-
 // runs one request on stream s; returns a status
 int execute(sparc_server *srv, Cluster &c, const Request &r, hipStream_t s, sparc_job_result &res)
 {
     int st;
-    const size_t es = elem_size(c.dtype);
-    std::vector<double> theta(c.ns);
+    int passes = 1;
+    double cut = c.lambda_f + 0.1;  // Sec. 4: previous Fermi level + 0.1 Ha
     if (!c.resident) {
         std::vector<sparc_atom> at(c.atoms.size());
         for (size_t i = 0; i < at.size(); ++i) at[i] = c.atoms[i].a;
         if ((st = sparc_op_create(&c.grid, c.veff.data(), (int)at.size(), at.data(), &c.op))) return st;
         c.ws_bytes = sparc_workspace_bytes(c.op, c.dtype, c.ns, 1);
-        c.rr_bytes = sparc_rr_workspace_bytes(c.op, c.dtype, c.ns);  // also covers the FP64 pass
-        c.rot_bytes = std::max(sparc_rotate_workspace_bytes(SPARC_F64, c.ns),
-                               sparc_rotate_workspace_bytes(SPARC_F32, c.ns));  // the first pass may be FP64
-        const size_t blk = (size_t)c.nd * c.ns * es;
+        c.rr_bytes = sparc_rr_workspace_bytes(c.op, c.dtype, c.ns);
+        c.rot_bytes = sparc_rotate_workspace_bytes(c.dtype, c.ns);
+        const size_t blk = (size_t)c.nd * c.ns * elem_size(c.dtype);
         if (hipMallocAsync(&c.X, blk, s) != hipSuccess || hipMallocAsync(&c.Y, blk, s) != hipSuccess ||
             hipMallocAsync(&c.ws, c.ws_bytes, s) != hipSuccess || hipMallocAsync(&c.rr, c.rr_bytes, s) != hipSuccess ||
             hipMallocAsync(&c.evec, (size_t)c.ns * c.ns * sizeof(double), s) != hipSuccess ||
             hipMallocAsync(&c.rot, c.rot_bytes, s) != hipSuccess)
             return fail(SPARC_E_NOMEM, "cluster allocation failed");
         c.resident = true;
-        // bounds from the device Lanczos; later requests reuse them
+        // bounds from the device Lanczos; later requests keep a0 and b
         const size_t lb = sparc_lanczos_workspace_bytes(c.op, srv->lanczos_k);
         void *lw = nullptr;
         if (hipMallocAsync(&lw, lb, s) != hipSuccess) return fail(SPARC_E_NOMEM, "Lanczos workspace allocation failed");
@@ -221,20 +188,31 @@ int execute(sparc_server *srv, Cluster &c, const Request &r, hipStream_t s, spar
         double ub = 0;
         sparc_upper_bound(c.op, &ub);
         if ((st = sparc_select_bounds(lt.data(), srv->lanczos_k, 8, 0.1, 1.01, ub, &c.a0, &c.a, &c.b))) return st;
-        if (c.dtype == SPARC_F32) {
-            st = first_pass_f64(c, s, theta);
-        } else {
+        if (c.dtype == SPARC_F64)
             st = launch_copy<double, double>(c.X0, c.ldx0, c.X, c.nd, c.nd, c.ns, s);
-            if (!st) st = run_pass(c, SPARC_F64, c.X, c.Y, c.ws, c.ws_bytes, s, theta);
-        }
-    } else {
-        st = run_pass(c, c.dtype, c.X, c.Y, c.ws, c.ws_bytes, s, theta);
+        else
+            st = launch_copy<float, float>(c.X0, c.ldx0, c.X, c.nd, c.nd, c.ns, s);
+        if (st) return st;
+        passes = srv->first_passes;  // the first SCF iteration (Sec. 3.4, last paragraph)
+        cut = c.a;
     }
-    if (st) return st;
-    SPARC_HIP(hipStreamSynchronize(s));
-    if (r.ritz) std::memcpy(r.ritz, theta.data(), theta.size() * sizeof(double));
-    res.lambda_min = theta.empty() ? 0.0 : theta[0];
-    res.updates = c.nd * (int64_t)c.ns * c.m;
+    std::vector<double> theta((size_t)passes * c.ns), lf(passes);
+    std::vector<int32_t> deg(passes);
+    ChefsiBuffers B{c.Y, c.nd, c.ws, c.ws_bytes, c.rr, c.rr_bytes, (double *)c.evec, c.rot, c.rot_bytes, nullptr};
+    int halvings = 0;
+    if ((st = chefsi_run(c.op, c.dtype, c.X, c.nd, c.ns, c.m, passes, c.ne, srv->kT, c.a0, cut, c.b, B, theta.data(),
+                         lf.data(), deg.data(), nullptr, s, &halvings)))
+        return st;
+    const double *last = theta.data() + (size_t)(passes - 1) * c.ns;
+    c.lambda_f = lf[passes - 1];
+    if (r.ritz) std::memcpy(r.ritz, last, (size_t)c.ns * sizeof(double));
+    res.lambda_min = last[0];
+    res.lambda_f = c.lambda_f;
+    res.passes = passes;
+    res.halvings = halvings;
+    int64_t degsum = 0;
+    for (int p = 0; p < passes; ++p) degsum += deg[p];
+    res.updates = c.nd * (int64_t)c.ns * degsum;
     return SPARC_OK;
 }
 
@@ -357,6 +335,16 @@ int sparc_server_create(const sparc_server_cfg *cfg, sparc_server **out)
     (void)hipGetDevice(&srv->device);
     srv->budget = cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : (size_t)250e9;
     srv->lanczos_k = cfg->lanczos_steps > 0 ? cfg->lanczos_steps : 40;
+    if (cfg->first_passes < 0 || cfg->first_passes > 64) {
+        delete srv;
+        return fail(SPARC_E_ARG, "first_passes must be in 0..64");
+    }
+    if (cfg->kT < 0 || !(cfg->kT == cfg->kT)) {
+        delete srv;
+        return fail(SPARC_E_ARG, "kT must be >= 0");
+    }
+    srv->first_passes = cfg->first_passes > 0 ? cfg->first_passes : 3;
+    srv->kT = cfg->kT > 0 ? cfg->kT : 1e-3;
     for (int i = 0; i < cfg->workers; ++i) srv->workers.emplace_back(worker_main, srv);
     *out = srv;
     return SPARC_OK;
@@ -374,6 +362,7 @@ int sparc_filter_submit(sparc_server *srv, const sparc_filter_job *job, uint64_t
             return fail(SPARC_E_ARG, "incomplete cluster description");
         if (d.dtype != SPARC_F64 && d.dtype != SPARC_F32) return fail(SPARC_E_ARG, "bad dtype");
         if (d.ns < 1 || d.m < 1) return fail(SPARC_E_BOUNDS, "ns and m must be >= 1");
+        if (!(d.ne > 0.0 && d.ne < 2.0 * d.ns)) return fail(SPARC_E_ARG, "need 0 < ne < 2 ns");
         if (d.grid.n[0] < 1 || d.grid.n[1] < 1 || d.grid.n[2] < 1) return fail(SPARC_E_SHAPE, "bad grid");
         const int64_t nd = (int64_t)d.grid.n[0] * d.grid.n[1] * d.grid.n[2];
         if (d.ldx0 < nd) return fail(SPARC_E_SHAPE, "leading dimension of X0 is below N_d");
@@ -398,6 +387,7 @@ int sparc_filter_submit(sparc_server *srv, const sparc_filter_job *job, uint64_t
         c.dtype = d.dtype;
         c.ns = d.ns;
         c.m = d.m;
+        c.ne = d.ne;
         c.X0 = d.X0;
         c.ldx0 = d.ldx0;
         c.v0 = d.v0;

@@ -1,0 +1,164 @@
+"""GPU parity of the repeated CheFSI passes (Sec. 3.4, last paragraph; the
+cutoff rule of Sec. 4) through sparc_chefsi against the oracle, pass by pass.
+
+Both sides get the same random block and the same filter bounds (from the
+oracle's Lanczos).  FP64: Ritz values and Fermi levels of every pass within
+1e-9 Ha (both sides compute in FP64 and differ only in rounding order; the
+filter amplifies nothing below the cutoff, so these differences stay near
+the rounding level), the density of the final block within 1e-9 of its
+maximum (the density depends on the occupied subspace only, not on signs or
+rotations inside degenerate levels).  FP32: the oracle follows the FP32 run's
+storage (operator, block, filter output and rotated orbitals rounded to
+FP32; Rayleigh-Ritz in FP64) but filters in FP64, where the library
+accumulates in FP32.  Ritz values of occupied states (below the Fermi level)
+are converged, so they move only to second order in that difference: within
+1e-6 Ha, as for the single FP32 pass.  Ritz values of the states above it are
+not converged and move to first order: within 2e-5 Ha (a relative difference
+of the filtered block of a few 1e-7 times a spectral width of tens of Ha)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1603_04334_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-9
+TOL32 = 1e-6
+TOL32_EMPTY = 2e-5
+PASSES = 3
+
+
+def _b():
+    from paper_1603_04334_amd import binding
+    binding.lib()
+    return binding
+
+
+def _case(name):
+    if name == "small":
+        c = inputs.SMALL
+        return inputs.case_cluster(c.name), c.ns, c.m, c.seed
+    # 40^3, 6 atoms, 48 orbitals (several 16-column tiles of the projection)
+    return inputs.make_cluster(40, 0.45, 6, 6, 1, seed=41, min_dist=1.5), 48, 16, 41
+
+
+def _bounds(cl, seed, ns):
+    _, _, theta = oracle.lanczos(cl, 40, inputs.lanczos_start(cl.nd, seed))
+    return oracle.select_bounds(theta, min(8, ns), ubound=oracle.upper_bound(cl))
+
+
+def _oracle_f32(cl, X, m, passes, ne, a0, a, b):
+    cl32 = inputs.round_cluster_f32(cl)
+    X = inputs.round_to_f32(X)
+    out = []
+    cut = a
+    for _ in range(passes):
+        Y = inputs.round_to_f32(oracle.cheb_filter(cl32, X, m, a0, cut, b))
+        th, vec, _, _ = oracle.rayleigh_ritz(cl, Y)
+        lf = oracle.fermi_level(th, ne)
+        X = inputs.round_to_f32(oracle.rotate(Y, vec))
+        out.append((th, lf))
+        cut = lf + 0.1
+    return out
+
+
+@pytest.mark.parametrize("name", ["small", "medium"])
+def test_chefsi_f64_passes(name):
+    b = _b()
+    cl, ns, m, seed = _case(name)
+    ne = b.default_electrons(ns)
+    a0, a, bb = _bounds(cl, seed, ns)
+    X0 = inputs.orbitals(cl.nd, ns, seed)
+    op = b.Operator(cl)
+    X = torch.from_numpy(X0).cuda()
+    rho = torch.empty(cl.nd, dtype=torch.float64, device="cuda")
+    theta, lf, deg = op.chefsi(X, m, PASSES, ne, a0, a, bb, rho=rho)
+    Xref, rec = oracle.chefsi_passes(cl, X0, m, PASSES, ne, a0, a, bb)
+    assert list(deg) == [m] * PASSES
+    for p, r in enumerate(rec):
+        et = np.abs(theta[p] - r["theta"]).max()
+        el = abs(lf[p] - r["lambda_f"])
+        print(f"{name} f64 pass {p}: cutoff {r['cutoff']:.6f} max |dtheta| {et:.2e} |dlambda_f| {el:.2e}", flush=True)
+        assert et <= TOL64 and el <= TOL64
+    torch.cuda.synchronize()
+    ref_rho = oracle.density(Xref, oracle.occupations(rec[-1]["theta"], rec[-1]["lambda_f"]), cl.h)
+    er = np.abs(rho.cpu().numpy() - ref_rho).max() / ref_rho.max()
+    print(f"{name} density rel err {er:.2e}; h^3 sum rho = {cl.h ** 3 * float(rho.sum()):.10f} (N_e {ne})", flush=True)
+    assert er <= TOL64
+    assert abs(cl.h ** 3 * float(rho.sum()) - ne) < 1e-8
+    # the rotated block is orthonormal
+    G = (X @ X.T).cpu().numpy()
+    assert np.abs(G - np.eye(ns)).max() < 1e-10
+
+
+@pytest.mark.parametrize("name", ["small", "medium"])
+def test_chefsi_f32_passes(name):
+    """Every pass in FP32 from the random block, as the server runs an FP32
+    cluster's first SCF iteration."""
+    b = _b()
+    cl, ns, m, seed = _case(name)
+    ne = b.default_electrons(ns)
+    a0, a, bb = _bounds(cl, seed, ns)
+    X0 = inputs.orbitals(cl.nd, ns, seed)
+    op = b.Operator(cl)
+    X = torch.from_numpy(X0).float().cuda()
+    theta, lf, deg = op.chefsi(X, m, PASSES, ne, a0, a, bb)
+    ref = _oracle_f32(cl, X0, m, PASSES, ne, a0, a, bb)
+    assert list(deg) == [m] * PASSES
+    for p, (th, l) in enumerate(ref):
+        d = np.abs(theta[p] - th)
+        occ = th < l
+        eo, ee = d[occ].max(), d[~occ].max()
+        print(f"{name} f32 pass {p}: max |dtheta| occupied {eo:.2e} empty {ee:.2e} (state {int(d.argmax())} of {ns}) "
+              f"|dlambda_f| {abs(lf[p] - l):.2e}", flush=True)
+        assert eo <= TOL32 and ee <= TOL32_EMPTY and abs(lf[p] - l) <= TOL32
+
+
+def test_chefsi_zero_column_halves_then_reports_breakdown():
+    """A zero column stays zero under the filter, so M_s is exactly singular
+    at every degree: the pass is retried at halved degrees down to 1, then
+    SPARC_E_BREAKDOWN is returned and X is left as it was."""
+    b = _b()
+    cl, ns, m, seed = _case("small")
+    a0, a, bb = _bounds(cl, seed, ns)
+    X0 = inputs.orbitals(cl.nd, ns, seed)
+    X0[3] = 0.0
+    op = b.Operator(cl)
+    X = torch.from_numpy(X0).cuda()
+    b.profile.reset()
+    b.profile.enable(True)
+    with pytest.raises(b.SparcError) as ei:
+        op.chefsi(X, m, 2, 8.0, a0, a, bb)
+    b.profile.enable(False)
+    assert ei.value.status == b.SPARC_E_BREAKDOWN
+    # degrees m, ceil(m/2), ..., 1; a filter of degree d makes d - 1 steps
+    # with Y_{k-1}, and its first step and the Rayleigh-Ritz H Y one without
+    degs = [m]
+    while degs[-1] > 1:
+        degs.append((degs[-1] + 1) // 2)
+    assert b.profile.read(0)[0] == sum(d - 1 for d in degs)
+    assert b.profile.read(3)[0] == 2 * len(degs)
+    b.profile.reset()
+    torch.cuda.synchronize()
+    assert np.array_equal(X.cpu().numpy(), X0)
+
+
+def test_chefsi_argument_errors():
+    b = _b()
+    cl, ns, m, seed = _case("small")
+    a0, a, bb = _bounds(cl, seed, ns)
+    op = b.Operator(cl)
+    X = torch.from_numpy(inputs.orbitals(cl.nd, ns, seed)).cuda()
+    for kw, code in ((dict(passes=0, ne=8.0), b.SPARC_E_ARG), (dict(passes=1, ne=2.0 * ns), b.SPARC_E_ARG),
+                     (dict(passes=1, ne=0.0), b.SPARC_E_ARG)):
+        with pytest.raises(b.SparcError) as ei:
+            op.chefsi(X, m, kw["passes"], kw["ne"], a0, a, bb)
+        assert ei.value.status == code
+    with pytest.raises(b.SparcError) as ei:
+        op.chefsi(X, m, 1, 8.0, a0, a, bb, ws=torch.empty(16, dtype=torch.uint8, device="cuda"))
+    assert ei.value.status == b.SPARC_E_WORKSPACE
+    with pytest.raises(b.SparcError) as ei:
+        op.chefsi(X, m, 1, 8.0, a, a0, bb)
+    assert ei.value.status == b.SPARC_E_BOUNDS

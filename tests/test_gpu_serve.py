@@ -1,12 +1,17 @@
-"""GPU tests of the request server (filtered-subspace passes on resident clusters).
+"""GPU tests of the request server (CheFSI passes on resident clusters).
 
-Each request runs the Chebyshev filter, the FP64 Rayleigh-Ritz step and the
-rotation (Sec. 3.4) on a cluster's resident orbitals; the first request of a
-cluster takes its filter bounds from the device Lanczos (Sec. 4).  Checked:
+A cluster's first request runs the first-SCF rule: three CheFSI passes
+(Chebyshev filter, FP64 Rayleigh-Ritz, Fermi level, rotation; Sec. 3.4) from
+the caller's random block, with bounds from the device Lanczos (Sec. 4);
+every later request runs one pass, with the cutoff at the previous Fermi
+level + 0.1 Ha (Sec. 4).  Checked:
  * the Ritz values of consecutive requests equal, bit for bit, those of the
    same library calls made directly on one stream;
  * against the FP64 oracle running the same passes: <= 1e-6 Ha (FP64 and FP32
-   orbitals);
+   orbitals; every pass of an FP32 cluster runs in FP32).  For FP32 clusters
+   the bound holds for the occupied states; the unconverged states above the
+   Fermi level move to first order in the FP32 accumulation of the filter
+   (the oracle filters in FP64 and rounds), bound 2e-5 Ha;
  * a cluster's results do not depend on what else the server runs;
  * admission never reserves more than the budget, and clusters that do not
    fit together run one after another;
@@ -26,7 +31,9 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL_RITZ = 1e-6
+TOL_RITZ_F32_EMPTY = 2e-5
 LANCZOS_K = 40
+FIRST_PASSES = 3
 
 # (edge, h, natoms, ns, m, seed): small clusters of uneven size
 CLUSTERS = [(24, 0.5, 2, 8, 12, 21), (28, 0.5, 3, 12, 14, 22), (20, 0.55, 1, 6, 10, 23),
@@ -92,44 +99,50 @@ def _serve(b, ids, steps, workers=4, budget=0, dtype=torch.float64, release=True
 
 
 def _direct(b, i, steps, dtype=torch.float64):
-    """The same passes through the library's entry points on one stream."""
+    """The same passes through the library's entry points on one stream:
+    three CheFSI passes for the first request, one for each later one, the
+    cutoff carried as the last Fermi level + 0.1 Ha."""
     (d, keep), cl, ns, m, seed, X0, v0 = _desc(b, i, dtype)
     op = b.Operator(cl)
     _, _, theta = op.lanczos(LANCZOS_K, v0)
     a0, a, bb = b.select_bounds(theta, 8, 0.1, 1.01, op.upper_bound())
     X = X0.clone()
     out = []
-    for _ in range(steps):
-        Y = op.cheb_filter(X, m, a0, a, bb)
-        th, Qt = op.rayleigh_ritz(Y)
-        X = b.rotate(Y, Qt)
-        out.append(th)
+    cut = a
+    for s in range(steps):
+        th, lf, deg = op.chefsi(X, m, FIRST_PASSES if s == 0 else 1, d.ne, a0, cut, bb)
+        out.append(th[-1])
+        cut = lf[-1] + 0.1
     torch.cuda.synchronize()
     return out
 
 
 def _oracle(i, steps, f32=False):
-    """The same passes in the oracle, with the server's precisions: Lanczos,
-    Rayleigh-Ritz and the first pass in FP64 on the FP64 operator; for an FP32
-    cluster the first pass starts from the FP32-rounded block, later filters
-    see the FP32-rounded operator, and the stored orbitals are FP32-rounded."""
+    """The same passes in the oracle, with the server's precisions: Lanczos and
+    Rayleigh-Ritz in FP64 on the FP64 operator; for an FP32 cluster the filter
+    sees the FP32-rounded operator and block and its output, like the rotated
+    orbitals, is rounded to FP32."""
     cl, ns, m, seed = _cluster(i)
+    ne = _b().default_electrons(ns)
     X = inputs.orbitals(cl.nd, ns, seed)
     cl32 = inputs.round_cluster_f32(cl) if f32 else cl
     if f32:
         X = inputs.round_to_f32(X)
     _, _, theta = oracle.lanczos(cl, LANCZOS_K, inputs.lanczos_start(cl.nd, seed))
-    a0, a, bb = oracle.select_bounds(theta, 8, ubound=oracle.upper_bound(cl))
+    a0, cut, bb = oracle.select_bounds(theta, 8, ubound=oracle.upper_bound(cl))
     out = []
     for s in range(steps):
-        Y = oracle.cheb_filter(cl if s == 0 else cl32, X, m, a0, a, bb)
-        if f32 and s > 0:
-            Y = inputs.round_to_f32(Y)
-        th, vec, _, _ = oracle.rayleigh_ritz(cl, Y)
-        X = oracle.rotate(Y, vec)
-        if f32:
-            X = inputs.round_to_f32(X)
-        out.append(th)
+        for _ in range(FIRST_PASSES if s == 0 else 1):
+            Y = oracle.cheb_filter(cl32, X, m, a0, cut, bb)
+            if f32:
+                Y = inputs.round_to_f32(Y)
+            th, vec, _, _ = oracle.rayleigh_ritz(cl, Y)
+            X = oracle.rotate(Y, vec)
+            if f32:
+                X = inputs.round_to_f32(X)
+            lf = oracle.fermi_level(th, ne)
+            cut = lf + 0.1
+        out.append((th, lf))
     return out
 
 
@@ -138,11 +151,13 @@ def test_serve_matches_direct_calls_bitwise():
     ritz, res, _ = _serve(b, [1], 3)
     ref = _direct(b, 1, 3)
     for s in range(3):
-        assert res[(1, s)]["status"] == 0 and res[(1, s)]["step"] == s
+        r = res[(1, s)]
+        assert r["status"] == 0 and r["step"] == s and r["halvings"] == 0
         assert np.array_equal(ritz[1][s], ref[s]), f"step {s}"
-        assert res[(1, s)]["lambda_min"] == ref[s][0]
+        assert r["lambda_min"] == ref[s][0]
         n, _, _, ns, m, _ = CLUSTERS[1]
-        assert res[(1, s)]["updates"] == n ** 3 * ns * m
+        passes = FIRST_PASSES if s == 0 else 1
+        assert r["passes"] == passes and r["updates"] == n ** 3 * ns * m * passes
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -154,10 +169,15 @@ def test_serve_oracle_parity(dtype):
     for i in ids:
         ref = _oracle(i, 3, f32=dtype == "f32")
         for s in range(3):
-            assert res[(i, s)]["status"] == 0
-            err = np.abs(ritz[i][s] - ref[s]).max()
-            print(f"cluster {i} step {s} {dtype} max |dtheta| {err:.3e}")
-            assert err <= TOL_RITZ
+            assert res[(i, s)]["status"] == 0 and res[(i, s)]["halvings"] == 0
+            th, lf = ref[s]
+            d = np.abs(ritz[i][s] - th)
+            occ = th < lf
+            eo, ee = d[occ].max(), d[~occ].max()
+            print(f"cluster {i} step {s} {dtype} max |dtheta| occupied {eo:.3e} empty {ee:.3e} "
+                  f"|dlambda_f| {abs(res[(i, s)]['lambda_f'] - lf):.3e}")
+            assert eo <= TOL_RITZ and abs(res[(i, s)]["lambda_f"] - lf) <= TOL_RITZ
+            assert ee <= (TOL_RITZ if dtype == "f64" else TOL_RITZ_F32_EMPTY)
 
 
 def test_serve_alone_vs_mix_bitwise():
@@ -187,7 +207,7 @@ def test_serve_wide_blocks_concurrent():
             assert np.array_equal(alone[i][s], mixed[i][s]), f"cluster {i} step {s}"
     ref = _oracle(7, 3)
     for s in range(3):
-        err = np.abs(mixed[7][s] - ref[s]).max()
+        err = np.abs(mixed[7][s] - ref[s][0]).max()
         print(f"wide cluster step {s} max |dtheta| {err:.3e}")
         assert err <= TOL_RITZ
 
