@@ -249,6 +249,60 @@ int sparc_fermi_level(const double *theta, int32_t ns, double ne, double kT, dou
 int sparc_density(int32_t dtype, const void *psi, int64_t ld, int64_t nd, int32_t ns, const double *occ, double h,
                   double *rho, void *stream);
 
+/* ------------------------------------------------------- nonlocal force */
+
+/* Workspace bytes of sparc_nonlocal_force for ns orbitals (0 on bad arguments). */
+size_t sparc_force_workspace_bytes(const sparc_op *op, int32_t ns);
+
+/* Nonlocal component of the atomic forces (Sec. 3.6, Eqs.
+ * NonlocForce:Discrete and NonLocForce:U:W, Alg. 4):
+ * f_J = -4 sum_n occ[n] sum_lm gamma_Jl Y_Jnlm W_Jnlm with
+ * Y_Jnlm = h^3 sum psi_n chi_Jlm and W_Jnlm = h^3 sum (grad_h psi_n) chi_Jlm,
+ * grad_h the finite-difference gradient of Eq. gradient:approximate (order
+ * 2 n_o, the operator's stencil radius, zero Dirichlet padding).  psi: the
+ * nd x ns block (column n at psi + n ld, dtype SPARC_F64 or SPARC_F32,
+ * widened to FP64 as it is read); occ: device FP64 array of ns occupations;
+ * force: device FP64 array of 3 natoms values, atom J's (x, y, z) at 3J
+ * (overwritten); ws: device workspace of sparc_force_workspace_bytes bytes.
+ * All sums run in FP64 in a fixed order.  The first call on an operator
+ * builds its gradient tables (FP64, about 4x the projector data) and is
+ * synchronous; later calls are asynchronous on stream.  With no atoms
+ * nothing is written.  Errors: SPARC_E_ARG, SPARC_E_SHAPE,
+ * SPARC_E_WORKSPACE, SPARC_E_ALIAS, SPARC_E_NOMEM, SPARC_E_HIP. */
+int sparc_nonlocal_force(const sparc_op *op, int32_t dtype, const void *psi, int64_t ld, int32_t ns, const double *occ,
+                         double *force, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------- CheFSI passes */
+
+/* Workspace bytes of sparc_chefsi (0 on bad arguments). */
+size_t sparc_chefsi_workspace_bytes(const sparc_op *op, int32_t dtype, int32_t ns);
+
+/* `passes` CheFSI passes on the orbital block X in place (Sec. 3.4): the
+ * Chebyshev filter (bounds a0, lambda_c, b), the FP64 Rayleigh-Ritz step, the
+ * Fermi level of the Ritz values (as sparc_fermi_level, with ne and kT) and
+ * the subspace rotation, after which X holds the Ritz vectors.  The first
+ * SCF iteration of a calculation runs about three passes from a random block
+ * (Sec. 3.4, last paragraph), every later one a single pass.  The first pass
+ * uses the cutoff a; every later pass the previous pass's Fermi level + 0.1 Ha
+ * (Sec. 4).  a0 and b are fixed (H does not change between the passes).
+ * A pass whose filtered block is numerically rank deficient (the Cholesky
+ * factorisation of M_s fails) is filtered again from the same X at half the
+ * degree, down to degree 1; degrees reports the degree each pass used.
+ * X: device block of dtype, ns columns, leading dimension ldx; ws: device
+ * workspace of sparc_chefsi_workspace_bytes bytes.  Host outputs (each may be
+ * NULL): theta (passes x ns Ritz values, pass by pass, ascending), lambda_f
+ * (passes Fermi levels), degrees (passes degrees).  rho: NULL, or a device
+ * FP64 array of N_d values receiving the density of the final block with
+ * the final occupations (as sparc_density).  Synchronous on stream.
+ * Errors: SPARC_E_ARG (bad dtype, passes < 1, ne outside (0, 2 ns), kT <= 0),
+ * SPARC_E_SHAPE, SPARC_E_BOUNDS (m < 1, not a0 < a < b, or a Fermi-level
+ * cutoff outside (a0, b)), SPARC_E_WORKSPACE, SPARC_E_ALIAS, SPARC_E_HIP,
+ * SPARC_E_BREAKDOWN (rank deficient at degree 1, or an eigensolver that did
+ * not converge).  On error X may hold the rotated block of an earlier pass. */
+int sparc_chefsi(const sparc_op *op, int32_t dtype, void *X, int64_t ldx, int32_t ns, int32_t m, int32_t passes,
+                 double ne, double kT, double a0, double a, double b, double *theta, double *lambda_f,
+                 int32_t *degrees, double *rho, void *ws, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------- batched filters */
 
 /* One filter of a batch: the arguments of sparc_cheb_filter for one cluster.
@@ -302,17 +356,22 @@ int sparc_batch_destroy(sparc_batch *batch);
 
 /* Server configuration: device memory budget for resident clusters (0 = 250 GB),
  * number of worker threads (requests on the device at once, each on its own
- * stream; 1..64) and Lanczos steps for the bounds (0 = 40). */
+ * stream; 1..64), Lanczos steps for the bounds (0 = 40), CheFSI passes of a
+ * cluster's first request (0 = 3, at most 64; Sec. 3.4, last paragraph) and
+ * the smearing k_B T of the Fermi level (0 = 1e-3 Ha, Sec. 4). */
 typedef struct {
     uint64_t hbm_budget_bytes;
     int32_t workers;
     int32_t lanczos_steps;
+    int32_t first_passes;
+    double kT;
 } sparc_server_cfg;
 
 /* A cluster: the operator (as for sparc_op_create), dtype, orbital count ns
  * and filter degree m, its initial orbitals X0 (device block of dtype, ns
- * columns, leading dimension ldx0) and the device FP64 Lanczos start v0 (N_d
- * values).  Host arrays are copied at submission; X0 and v0 must be complete
+ * columns, leading dimension ldx0), the device FP64 Lanczos start v0 (N_d
+ * values) and its electron count ne (0 < ne < 2 ns; the paper sizes
+ * ns = ne/2 + 30, Sec. 4).  Host arrays are copied at submission; X0 and v0 must be complete
  * (their producing work finished) when the first request is submitted, are
  * read when the cluster is admitted and must stay valid until that request is
  * done.  The server copies X0, so the caller's block is never written. */
@@ -327,22 +386,22 @@ typedef struct {
     const void *X0;
     int64_t ldx0;
     const double *v0;
+    double ne;
 } sparc_cluster_desc;
 
-/* One request: a filtered-subspace pass (Sec. 3.4: Chebyshev filter, FP64
- * Rayleigh-Ritz, rotation) on the resident orbitals of cluster `cluster` (an
- * id chosen by the caller).  The first request of a cluster carries its
- * description; it builds the operator, copies X0 and computes the filter
- * bounds with the device Lanczos (a = theta_8 + 0.1, b = 1.01 theta_max capped
- * by the upper bound), which the cluster's later requests reuse.  The rotated
- * orbitals stay resident for the next request.  The first pass of an FP32
- * cluster runs in FP64 from the caller's block (a filter applied to an
- * unconverged block concentrates every column on the lowest eigenvectors,
- * beyond what FP32 resolves) and stores the rotated orbitals rounded to FP32;
- * later passes run in FP32.  release = 1 frees the
- * cluster's device memory after this request.  ritz: optional host buffer of
- * ns doubles receiving the Ritz values; it must stay valid until the request
- * is done. */
+/* One request: the eigensolve of one SCF iteration on the resident orbitals
+ * of cluster `cluster` (an id chosen by the caller), in the cluster's dtype
+ * throughout.  The first request of a cluster carries its description; it
+ * builds the operator, copies X0, computes the filter bounds with the device
+ * Lanczos (a0 = theta_1, cutoff theta_8 + 0.1, b = 1.01 theta_max capped by
+ * the upper bound) and runs the first-SCF rule: first_passes CheFSI passes
+ * (as sparc_chefsi) from X0 without a density update (Sec. 3.4, last
+ * paragraph).  Every later request runs one pass on the resident rotated
+ * orbitals.  After the first pass every cutoff is the previous pass's Fermi
+ * level + 0.1 Ha (Sec. 4), carried across requests; a0 and b are kept.
+ * release = 1 frees the cluster's device memory after this request.  ritz:
+ * optional host buffer of ns doubles receiving the Ritz values of the
+ * request's last pass; it must stay valid until the request is done. */
 typedef struct {
     uint64_t cluster;
     const sparc_cluster_desc *desc;
@@ -353,14 +412,19 @@ typedef struct {
 /* Outcome of a request: status (SPARC_OK or the failing call's code;
  * SPARC_E_JOB when an earlier request of the cluster failed), 0-based index of
  * the request within its cluster, steady-clock times (seconds, as
- * sparc_clock) of submission, start and completion, lowest Ritz value, and
- * N_d * ns * m filtered orbital*gridpoint updates. */
+ * sparc_clock) of submission, start and completion, lowest Ritz value and
+ * Fermi level of the last pass, N_d * ns * (sum of the passes' degrees)
+ * filtered orbital*gridpoint updates, the number of passes run and of degree
+ * halvings (rank-deficient passes redone at half the degree). */
 typedef struct {
     int32_t status;
     int32_t step;
     double t_submit, t_start, t_end;
     double lambda_min;
     int64_t updates;
+    double lambda_f;
+    int32_t passes;
+    int32_t halvings;
     char error[128];  /* message of the failing call (empty on success) */
 } sparc_job_result;
 

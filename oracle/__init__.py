@@ -28,6 +28,10 @@ Functions and the passages they follow:
 * ``chefsi_passes``     Sec. 3.4 last paragraph and Sec. 4: repeated CheFSI
                         passes (filter, Rayleigh-Ritz, Fermi level, rotation)
                         with the cutoff set to the previous Fermi level + 0.1 Ha.
+* ``gradient_weights``  Sec. 3.1, the weights of Eq. gradient:approximate.
+* ``gradient``          Sec. 3.1 Eq. gradient:approximate with zero Dirichlet padding.
+* ``nonlocal_force``    Sec. 3.6 Eqs. NonlocForce:Discrete and NonLocForce:U:W
+                        (Alg. 4): Y_Jnlm, W_Jnlm and the nonlocal atomic force.
 * ``dense_hamiltonian`` brute-force N_d x N_d matrix for tiny grids.
 * ``cheb_closed_form``  C_m(x) from its trigonometric/hyperbolic definition.
 """
@@ -346,6 +350,74 @@ def density(Psi: np.ndarray, g, h: float) -> np.ndarray:
     return 2.0 / h ** 3 * rho
 
 
+# ----------------------------------------------------------------------------- gradient and nonlocal force
+
+def gradient_weights(no: int, h: float) -> np.ndarray:
+    """w~_1..w~_{n_o} of Eq. gradient:approximate (Sec. 3.1):
+    w~_p = (-1)^(p+1) / (h p) * (n_o!)^2 / ((n_o - p)! (n_o + p)!).  Returned
+    with index 0 unused (zero), so that w[p] is w~_p."""
+    w = np.zeros(no + 1)
+    f = math.factorial
+    for p in range(1, no + 1):
+        w[p] = (-1.0) ** (p + 1) / (h * p) * (f(no) ** 2 / (f(no - p) * f(no + p)))
+    return w
+
+
+def gradient(n: Sequence[int], h: float, no: int, f: np.ndarray) -> np.ndarray:
+    """nabla_h f of Eq. gradient:approximate on one grid function: (3, N_d),
+    component d the central difference along axis d (e_1 along the slowest
+    index i), with f = 0 at every index outside the grid (Sec. 3.1)."""
+    w = gradient_weights(no, h)
+    F = np.zeros((n[0] + 2 * no, n[1] + 2 * no, n[2] + 2 * no))
+    F[no:no + n[0], no:no + n[1], no:no + n[2]] = np.asarray(f, dtype=np.float64).reshape(n)
+    out = np.zeros((3,) + tuple(n))
+    for d in range(3):
+        for p in range(1, no + 1):
+            plus = [slice(no, no + n[a]) for a in range(3)]
+            minus = [slice(no, no + n[a]) for a in range(3)]
+            plus[d] = slice(no + p, no + p + n[d])
+            minus[d] = slice(no - p, no - p + n[d])
+            out[d] += w[p] * (F[tuple(plus)] - F[tuple(minus)])
+    return out.reshape(3, -1)
+
+
+def nonlocal_force(cluster, Psi: np.ndarray, g) -> np.ndarray:
+    """Nonlocal atomic forces f_J (natoms, 3) of Sec. 3.6 Eq.
+    NonlocForce:Discrete, following Alg. 4: for each atom J, the gradient
+    nabla_h psi_n at the points of J's cube (Eq. gradient:approximate, psi = 0
+    off the grid), Y_Jnlm = h^3 sum psi_n chi_Jlm and W_Jnlm = h^3 sum
+    (nabla_h psi_n) chi_Jlm over the cube (Eq. NonLocForce:U:W), then
+    f_J = -4 sum_n g_n sum_lm gamma_Jl Y_Jnlm W_Jnlm.  Psi: (ns, nd) block;
+    g: the ns occupations."""
+    Psi = _block(Psi, cluster.nd)
+    g = np.asarray(g, dtype=np.float64)
+    n, h, no = cluster.n, cluster.h, cluster.radius
+    w = gradient_weights(no, h)
+    h3 = h ** 3
+    ns = Psi.shape[0]
+    f = np.zeros((len(cluster.atoms), 3))
+    for k in range(ns):
+        P = np.zeros((n[0] + 2 * no, n[1] + 2 * no, n[2] + 2 * no))
+        P[no:no + n[0], no:no + n[1], no:no + n[2]] = Psi[k].reshape(n)
+        for J, a in enumerate(cluster.atoms):
+            lo, ext = a.lo, a.ext
+            cube = tuple(slice(no + lo[d], no + lo[d] + ext[d]) for d in range(3))
+            psi = P[cube]
+            grad = np.zeros((3,) + tuple(ext))
+            for d in range(3):
+                for p in range(1, no + 1):
+                    plus, minus = list(cube), list(cube)
+                    plus[d] = slice(no + lo[d] + p, no + lo[d] + ext[d] + p)
+                    minus[d] = slice(no + lo[d] - p, no + lo[d] + ext[d] - p)
+                    grad[d] += w[p] * (P[tuple(plus)] - P[tuple(minus)])
+            for q in range(a.nproj):
+                Y = h3 * np.sum(psi * a.chi[q])
+                for d in range(3):
+                    W = h3 * np.sum(grad[d] * a.chi[q])
+                    f[J, d] += -4.0 * g[k] * a.gamma[q] * Y * W
+    return f
+
+
 # ----------------------------------------------------------------------------- CheFSI passes
 
 CUTOFF_SHIFT = 0.1  # lambda_c = previous Fermi energy + 0.1 Ha (Sec. 4)
@@ -404,11 +476,23 @@ def fornberg_second_derivative(no: int):
 
     An independent route to the Laplacian weights (Gauss-Jordan over
     fractions.Fraction); returns c_0..c_no (symmetric stencil)."""
+    return _fornberg_central(no, 2)
+
+
+def fornberg_first_derivative(no: int):
+    """Exact rational central weights of d/dx on the unit-spaced stencil (the
+    same moment conditions with q! [q == 1]); returns c_0..c_no (c_0 = 0,
+    c_{-p} = -c_p).  An independent route to the gradient weights."""
+    return _fornberg_central(no, 1)
+
+
+def _fornberg_central(no: int, order: int):
     from fractions import Fraction
 
     pts = list(range(-no, no + 1))
     N = len(pts)
-    A = [[Fraction(j) ** q for j in pts] + [Fraction(2 if q == 2 else 0)] for q in range(N)]
+    rhs = Fraction(math.factorial(order))
+    A = [[Fraction(j) ** q for j in pts] + [rhs if q == order else Fraction(0)] for q in range(N)]
     for col in range(N):
         piv = next(r for r in range(col, N) if A[r][col] != 0)
         A[col], A[piv] = A[piv], A[col]

@@ -58,13 +58,15 @@ class sparc_batch_job(ctypes.Structure):
 
 
 class sparc_server_cfg(ctypes.Structure):
-    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("workers", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32)]
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("workers", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32),
+                ("first_passes", ctypes.c_int32), ("kT", ctypes.c_double)]
 
 
 class sparc_cluster_desc(ctypes.Structure):
     _fields_ = [("grid", sparc_grid), ("veff", ctypes.POINTER(ctypes.c_double)), ("natoms", ctypes.c_int32),
                 ("atoms", ctypes.POINTER(sparc_atom)), ("dtype", ctypes.c_int32), ("ns", ctypes.c_int32),
-                ("m", ctypes.c_int32), ("X0", ctypes.c_void_p), ("ldx0", ctypes.c_int64), ("v0", ctypes.c_void_p)]
+                ("m", ctypes.c_int32), ("X0", ctypes.c_void_p), ("ldx0", ctypes.c_int64), ("v0", ctypes.c_void_p),
+                ("ne", ctypes.c_double)]
 
 
 class sparc_filter_job(ctypes.Structure):
@@ -75,7 +77,8 @@ class sparc_filter_job(ctypes.Structure):
 class sparc_job_result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("step", ctypes.c_int32), ("t_submit", ctypes.c_double),
                 ("t_start", ctypes.c_double), ("t_end", ctypes.c_double), ("lambda_min", ctypes.c_double),
-                ("updates", ctypes.c_int64), ("error", ctypes.c_char * 128)]
+                ("updates", ctypes.c_int64), ("lambda_f", ctypes.c_double), ("passes", ctypes.c_int32),
+                ("halvings", ctypes.c_int32), ("error", ctypes.c_char * 128)]
 
 
 _lib = None
@@ -106,6 +109,11 @@ _SIGS = {
     "sparc_stream_copy": (_i32, [_vp, _vp, _sz, _vp]),
     "sparc_fermi_level": (_i32, [_dp, _i32, _dbl, _dbl, _dp, _dp]),
     "sparc_density": (_i32, [_i32, _vp, _i64, _i64, _i32, _vp, _dbl, _vp, _vp]),
+    "sparc_force_workspace_bytes": (_sz, [_vp, _i32]),
+    "sparc_nonlocal_force": (_i32, [_vp, _i32, _vp, _i64, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "sparc_chefsi_workspace_bytes": (_sz, [_vp, _i32, _i32]),
+    "sparc_chefsi": (_i32, [_vp, _i32, _vp, _i64, _i32, _i32, _i32, _dbl, _dbl, _dbl, _dbl, _dbl, _dp, _dp,
+                            ctypes.POINTER(_i32), _vp, _vp, _sz, _vp]),
     "sparc_h_apply_noalloc": (_i32, [_vp, _i32, _vp, _i64, _vp, _i64, _i32, _vp]),
     "sparc_noalloc_scratch_bytes": (_sz, []),
     "sparc_last_error": (ctypes.c_char_p, []),
@@ -302,6 +310,44 @@ class Operator:
         # evec is column-major ns x ns: as a torch (ns, ns) row-major tensor it is Q^T
         return theta, evec
 
+    def nonlocal_force(self, Psi, occ, force=None, ws=None, stream=None):
+        """Nonlocal atomic forces (natoms, 3) FP64 of the (ns, nd) block Psi with
+        device FP64 occupations occ (ns,)."""
+        import torch
+        ns, ld = _block(Psi, self.nd, "Psi")
+        natoms = len(self.cluster.atoms)
+        if occ.dtype != torch.float64 or occ.numel() != ns or not occ.is_cuda or not occ.is_contiguous():
+            raise ValueError("occ must be a contiguous device float64 tensor of ns entries")
+        if force is None:
+            force = torch.zeros(max(natoms, 1), 3, dtype=torch.float64, device=Psi.device)
+        if ws is None:
+            ws = torch.empty(max(1, int(lib().sparc_force_workspace_bytes(self.handle, ns))), dtype=torch.uint8,
+                             device=Psi.device)
+        check(lib().sparc_nonlocal_force(self.handle, _dtype_code(Psi), _ptr(Psi), ld, ns, _ptr(occ), _ptr(force),
+                                         _ptr(ws), ws.numel(), _stream(stream)), "sparc_nonlocal_force")
+        return force[:natoms]
+
+    def chefsi(self, X, m: int, passes: int, ne: float, a0: float, a: float, b: float, kT: float = 1e-3,
+               rho=None, ws=None, stream=None):
+        """``passes`` CheFSI passes on X in place; returns (theta (passes, ns),
+        lambda_f (passes,), degrees (passes,))."""
+        import torch
+        ns, ld = _block(X, self.nd, "X")
+        dt = _dtype_code(X)
+        if ws is None:
+            ws = torch.empty(max(1, int(lib().sparc_chefsi_workspace_bytes(self.handle, dt, ns))), dtype=torch.uint8,
+                             device=X.device)
+        if rho is not None and (rho.dtype != torch.float64 or rho.numel() != self.nd or not rho.is_contiguous()):
+            raise ValueError("rho must be a contiguous float64 tensor of N_d entries")
+        theta = np.zeros((passes, ns))
+        lf = np.zeros(passes)
+        deg = np.zeros(passes, dtype=np.int32)
+        check(lib().sparc_chefsi(self.handle, dt, _ptr(X), ld, ns, int(m), int(passes), float(ne), float(kT), float(a0),
+                                 float(a), float(b), theta.ctypes.data_as(_dp), lf.ctypes.data_as(_dp),
+                                 deg.ctypes.data_as(ctypes.POINTER(_i32)), _ptr(rho) if rho is not None else None,
+                                 _ptr(ws), ws.numel(), _stream(stream)), "sparc_chefsi")
+        return theta, lf, deg
+
     def set_launch(self, dtype_code: int, tile_z: int = 0, tile_y: int = 0, chunk_x: int = 0, col_group: int = 0):
         check(lib().sparc_op_set_launch(self.handle, dtype_code, tile_z, tile_y, chunk_x, col_group),
               "sparc_op_set_launch")
@@ -459,8 +505,15 @@ def _cluster_arrays(cluster):
     return g, atoms, veff, keep
 
 
-def cluster_desc(cluster, X0, v0, m: int):
-    """sparc_cluster_desc for an inputs.Cluster with device tensors X0 (ns, ld) and v0 (N_d, float64)."""
+def default_electrons(ns: int) -> float:
+    """Electron count for ns orbitals by the paper's sizing rule ns = N_e/2 + 30
+    (Sec. 4); for blocks of 60 orbitals or fewer, half of them occupied."""
+    return float(2 * (ns - 30)) if ns > 60 else float(ns)
+
+
+def cluster_desc(cluster, X0, v0, m: int, ne: float = None):
+    """sparc_cluster_desc for an inputs.Cluster with device tensors X0 (ns, ld)
+    and v0 (N_d, float64); ne defaults to ``default_electrons(ns)``."""
     g, atoms, veff, keep = _cluster_arrays(cluster)
     ns, ld = _block(X0, cluster.nd, "X0")
     d = sparc_cluster_desc()
@@ -474,11 +527,12 @@ def cluster_desc(cluster, X0, v0, m: int):
     d.X0 = _ptr(X0)
     d.ldx0 = ld
     d.v0 = _ptr(v0)
+    d.ne = float(default_electrons(ns) if ne is None else ne)
     return d, keep + [atoms, X0, v0]
 
 
 def cluster_footprint(cluster, X0, v0, m: int, lanczos_steps: int = 0) -> int:
-    d, keep = cluster_desc(cluster, X0, v0, m)
+    d, keep = cluster_desc(cluster, X0, v0, m, ne=1.0)
     return int(lib().sparc_cluster_footprint(ctypes.byref(d), int(lanczos_steps)))
 
 
@@ -487,10 +541,11 @@ def clock() -> float:
 
 
 class Server:
-    """Request server: one filtered-subspace pass per request on resident clusters."""
+    """Request server: one SCF iteration's CheFSI passes per request on resident clusters."""
 
-    def __init__(self, workers: int = 4, budget: int = 0, lanczos_steps: int = 0):
-        cfg = sparc_server_cfg(int(budget), int(workers), int(lanczos_steps))
+    def __init__(self, workers: int = 4, budget: int = 0, lanczos_steps: int = 0, first_passes: int = 0,
+                 kT: float = 0.0):
+        cfg = sparc_server_cfg(int(budget), int(workers), int(lanczos_steps), int(first_passes), float(kT))
         h = _vp()
         check(lib().sparc_server_create(ctypes.byref(cfg), ctypes.byref(h)), "sparc_server_create")
         self.handle = h
@@ -517,7 +572,8 @@ class Server:
             return None
         check(st, "sparc_filter_poll")
         return {"status": r.status, "step": r.step, "t_submit": r.t_submit, "t_start": r.t_start, "t_end": r.t_end,
-                "lambda_min": r.lambda_min, "updates": r.updates, "error": r.error.decode(errors="replace")}
+                "lambda_min": r.lambda_min, "updates": r.updates, "lambda_f": r.lambda_f, "passes": r.passes,
+                "halvings": r.halvings, "error": r.error.decode(errors="replace")}
 
     def stats(self):
         d, p, r, u = _i64(), _i64(), _i64(), ctypes.c_uint64()

@@ -387,6 +387,10 @@ int sparc_op_destroy(sparc_op *op)
     (void)hipFree(op->d_nl_blk_pt);
     (void)hipFree(op->d_nl_blk_at);
     (void)hipFree(op->d_nl_blk_atoms);
+    (void)hipFree(op->d_fatoms);
+    (void)hipFree(op->d_fbox_off);
+    (void)hipFree(op->d_ffun);
+    (void)hipFree(op->d_fgamma);
     delete op;
     return SPARC_OK;
 }

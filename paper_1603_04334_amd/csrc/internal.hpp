@@ -85,6 +85,16 @@ struct sparc_op {
     int tune_chunk[2] = {0, 0};
     int tune_ns[2] = {-1, -1};  // block width the launch choice was tuned for; -1: every width
     int tune_group[2] = {0, 0};  // column group of the vector step (0 = library choice)
+    // nonlocal-force tables, built on the first sparc_nonlocal_force call:
+    // per atom four gather records (the cube with chi, and for each axis d
+    // the cube widened by the stencil radius along d with -grad_d chi), their
+    // grid offsets and function values (FP64), and gamma per projector
+    mutable std::mutex force_mu;
+    mutable bool force_ready = false;
+    mutable sparc::AtomDev *d_fatoms = nullptr;
+    mutable int *d_fbox_off = nullptr;
+    mutable double *d_ffun = nullptr;
+    mutable double *d_fgamma = nullptr;
 };
 
 namespace sparc {
@@ -192,6 +202,36 @@ int launch_h_step(const sparc_op *op, int dtype, const void *yk, int64_t ldk, co
 // evec column-major and M-orthonormal; info = 0 or the failing Cholesky column
 int launch_small_sygv(const double *Hs, const double *Ms, int n, double *theta, double *evec, int *info,
                       hipStream_t stream);
+
+// true when the last sparc_rayleigh_ritz of this thread failed because the
+// Cholesky factorisation of M_s broke down (rank-deficient filtered block)
+extern thread_local bool g_rr_rank_deficient;
+
+// buffers of the CheFSI passes: the filtered block Y (ldy), the filter's
+// workspace, the Rayleigh-Ritz workspace, the ns x ns eigenvectors, the
+// rotation's workspace and ns device doubles for the occupations
+struct ChefsiBuffers {
+    void *Y;
+    int64_t ldy;
+    void *fws;
+    size_t fws_bytes;
+    void *rr;
+    size_t rr_bytes;
+    double *evec;
+    void *rot;
+    size_t rot_bytes;
+    double *occ;
+};
+
+// `passes` CheFSI passes on X in place (filter, Rayleigh-Ritz, Fermi level,
+// rotation); the cutoff of every pass after the first is the previous Fermi
+// level + 0.1 Ha; a pass whose block turns out rank deficient is redone at
+// half the degree.  theta (passes x ns), lambda_f, degrees: host outputs
+// (may be null); rho: device density of the final block (may be null);
+// halvings: number of degree halvings (may be null).  Synchronous.
+int chefsi_run(const sparc_op *op, int dtype, void *X, int64_t ldx, int ns, int m, int passes, double ne, double kT,
+               double a0, double a, double b, const ChefsiBuffers &B, double *theta, double *lambda_f,
+               int32_t *degrees, double *rho, hipStream_t s, int *halvings);
 
 // profiling hooks (no-ops unless enabled)
 struct ProfScope {
