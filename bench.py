@@ -44,6 +44,8 @@ def parse():
     p.add_argument("--no-fp64-compare", action="store_true")
     p.add_argument("--no-secondary", action="store_true", help="skip the medium-cluster and small-cluster lines")
     p.add_argument("--no-batch", action="store_true", help="skip the batched uneven-cluster measurement")
+    p.add_argument("--no-next", action="store_true",
+                   help="skip the first-SCF, density, force and electrostatic-potential measurements")
     p.add_argument("--batch-only", action="store_true", help="print only the batched measurement")
     p.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     p.add_argument("--serve-only", action="store_true", help="print only the serving measurement")
@@ -422,6 +424,124 @@ def secondary(args):
     return out
 
 
+def _event_ms(fn, reps):
+    """Average device time of fn over reps runs, HIP events on the current stream."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def next_rows(case, cl, op, dtype):
+    """The rows after the filtered-subspace pass, on the same cluster: the
+    first SCF iteration (three CheFSI passes from the random block, cutoff =
+    last Fermi level + 0.1 Ha), one later pass, the Fermi level, the density
+    of the rotated block, the nonlocal forces and the electrostatic potential
+    of a neutral synthetic charge on the same grid."""
+    import torch
+    from paper_1603_04334_amd import binding, inputs
+    dt = torch.float32 if dtype == "f32" else torch.float64
+    s = 4 if dtype == "f32" else 8
+    nd, ns, m = cl.nd, case.ns, case.m
+    ne = 2.0 * (ns - 30)  # N_s = N_e / 2 + 30 (Sec. 4)
+    out = {"electrons": ne}
+    X = inputs.device_orbitals(nd, ns, case.seed, dt)
+    v0 = torch.from_numpy(inputs.lanczos_start(nd, case.seed)).cuda()
+    _, _, theta = op.lanczos(KSTEPS_LANCZOS, v0)
+    a0, a, bb = binding.select_bounds(theta, 8, ubound=op.upper_bound())
+    code = binding.SPARC_F32 if dtype == "f32" else binding.SPARC_F64
+    ws = torch.empty(int(binding.lib().sparc_chefsi_workspace_bytes(op.handle, code, ns)), dtype=torch.uint8,
+                     device="cuda")
+    rho = torch.empty(nd, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    th, lf, deg = op.chefsi(X, m, 3, ne, a0, a, bb, rho=rho, ws=ws)
+    t1 = time.perf_counter()
+    th2, lf2, deg2 = op.chefsi(X, m, 1, ne, a0, float(lf[-1]) + 0.1, bb, ws=ws)
+    t2 = time.perf_counter()
+    out["first_scf"] = {"passes": 3, "ms": (t1 - t0) * 1e3, "degrees": [int(d) for d in deg],
+                        "cutoffs": [a] + [float(v) + 0.1 for v in lf[:-1]], "lambda_f": [float(v) for v in lf],
+                        "lowest_ritz": [float(t[0]) for t in th],
+                        "density_integral": float(rho.sum().item()) * cl.h ** 3}
+    out["later_pass"] = {"ms": (t2 - t1) * 1e3, "cutoff": float(lf[-1]) + 0.1, "lambda_f": float(lf2[0]),
+                         "degree": int(deg2[0])}
+    del ws
+    # Fermi level (host)
+    reps = 200
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lfv, occ = binding.fermi_level(th2[0], ne)
+    out["fermi_level"] = {"us": (time.perf_counter() - t0) / reps * 1e6, "lambda_f": lfv, "states": ns}
+    # density of the rotated block
+    g = torch.from_numpy(occ).cuda()
+    ms = _event_ms(lambda: binding.density(X, g, cl.h, rho=rho), 5)
+    byt = s * nd * ns + 8 * nd
+    out["density"] = {"ms": ms, "alg_bytes": byt, "gbs": byt / (ms * 1e-3) / 1e9,
+                      "frac_of_peak": byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "bytes": "s N_d N_s read + 8 N_d written"}
+    # nonlocal forces
+    fws = torch.empty(int(binding.lib().sparc_force_workspace_bytes(op.handle, ns)), dtype=torch.uint8,
+                      device="cuda")
+    f = torch.empty(len(cl.atoms), 3, dtype=torch.float64, device="cuda")
+    t0 = time.perf_counter()
+    op.nonlocal_force(X, g, force=f, ws=fws)
+    torch.cuda.synchronize()
+    first = (time.perf_counter() - t0) * 1e3
+    ms = _event_ms(lambda: op.nonlocal_force(X, g, force=f, ws=fws), 5)
+    R = cl.radius
+    pts = 0
+    for at in cl.atoms:
+        e = list(at.ext)
+        pts += int(np.prod(e))
+        for d in range(3):
+            lo = max(0, at.lo[d] - R)
+            hi = min(cl.n[d], at.lo[d] + at.ext[d] + R)
+            ee = list(e)
+            ee[d] = hi - lo
+            pts += int(np.prod(ee))
+    byt = s * pts * ns
+    out["nonlocal_force"] = {"ms": ms, "first_call_ms_with_tables": first, "orbital_bytes_read": byt,
+                             "gbs": byt / (ms * 1e-3) / 1e9, "atoms": len(cl.atoms),
+                             "bytes": "s N_s per point of each atom's cube and its three widened gradient boxes"}
+    del fws, X, rho
+    torch.cuda.empty_cache()
+    # electrostatic potential of a neutral synthetic charge on the same grid
+    n = (case.n,) * 3
+    h = case.h
+    ax = [(torch.arange(1, case.n + 1, device="cuda", dtype=torch.float64) - 0.5 * (case.n + 1)) * h] * 3
+    Xg, Yg, Zg = torch.meshgrid(*ax, indexing="ij")
+    charge = torch.zeros(n, dtype=torch.float64, device="cuda")
+    cen = 0.5 * (case.n + 1) * h
+    for at in cl.atoms:
+        r2 = (Xg - (at.pos[0] - cen)) ** 2 + (Yg - (at.pos[1] - cen)) ** 2 + (Zg - (at.pos[2] - cen)) ** 2
+        for sig, q in ((0.6, -at.Z), (1.1, at.Z)):
+            charge += q * torch.exp(-r2 / (2 * sig * sig)) / (2 * np.pi * sig * sig) ** 1.5
+    charge = charge.reshape(-1).contiguous()
+    del Xg, Yg, Zg
+    P = binding.Poisson(n, h)
+    pws = torch.empty(int(binding.lib().sparc_poisson_workspace_bytes(P.handle)), dtype=torch.uint8, device="cuda")
+    phi = torch.zeros(nd, dtype=torch.float64, device="cuda")
+    P.solve(charge, phi=phi, tol=1e-10, ws=pws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, it, res, _ = P.solve(charge, phi=phi, tol=1e-10, ws=pws)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    per_it = 14 * 8 * nd  # matvec 2, p.q 2, x/r/z update 7, p update 3 vector passes
+    out["poisson"] = {"grid": list(n), "tol": 1e-10, "iterations": it, "rel_resid": res, "ms": ms,
+                      "ms_per_iteration": ms / max(it, 1), "bytes_per_iteration": per_it,
+                      "gbs": per_it * it / (ms * 1e-3) / 1e9, "lmax": 6, "block": [4, 4, 4]}
+    del P, pws, phi, charge
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(case, cl, op, bounds, ncols=16):
     """The C oracle's FP64 filter on the host's OpenMP threads, on a seeded
     subset of the workload's orbitals (the first ncols columns of the same
@@ -547,6 +667,10 @@ def main():
         d = np.abs(main_res["first_ritz"] - r64["first_ritz"])
         out["ritz_f32_vs_f64"] = {"max_abs_diff_ha": float(d.max()), "tolerance_ha": 1e-6,
                                   "lowest": float(main_res["first_ritz"][0])}
+    if not args.no_next:
+        print("bench: first SCF iteration, density, forces, electrostatic potential", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        out["next_rows"] = next_rows(case, cl, op, args.dtype)
     if not args.no_secondary and args.workload == "large":
         print("bench: medium and small clusters", file=sys.stderr, flush=True)
         out.update(secondary(args))

@@ -272,6 +272,46 @@ size_t sparc_force_workspace_bytes(const sparc_op *op, int32_t ns);
 int sparc_nonlocal_force(const sparc_op *op, int32_t dtype, const void *psi, int64_t ld, int32_t ns, const double *occ,
                          double *force, void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------- electrostatic potential */
+
+typedef struct sparc_poisson sparc_poisson;
+
+/* A Poisson solver for the grid (n, h, stencil radius n_o as for
+ * sparc_op_create): the operator -(1/4 pi) lap_h with zero Dirichlet padding
+ * (Sec. 3.3, Eq. FD:PoissonDiscrete), the multipole boundary correction to
+ * order lmax (0..6; the paper uses 6, Sec. 4), and the block-Jacobi
+ * preconditioner on blocks of block[0] x block[1] x block[2] nodes (each edge
+ * 1..8, at most 256 nodes; NULL = 4 x 4 x 4; blocks at the high end of an
+ * axis are cut short), whose block inverses are formed here (host, FP64).
+ * The expansion centre is the centre of the domain.  Allocates on the
+ * current device.  Errors: SPARC_E_ARG, SPARC_E_SHAPE, SPARC_E_NOMEM,
+ * SPARC_E_HIP. */
+int sparc_poisson_create(const sparc_grid *grid, int32_t lmax, const int32_t *block, sparc_poisson **out);
+
+/* Free the solver.  NULL is accepted. */
+int sparc_poisson_destroy(sparc_poisson *p);
+
+/* Workspace bytes of sparc_poisson_solve (four grid vectors, the boundary
+ * slabs and the reduction partials). */
+size_t sparc_poisson_workspace_bytes(const sparc_poisson *p);
+
+/* Electrostatic potential of the total charge c = rho + b (Sec. 3.3):
+ * -(1/4 pi) lap_h phi = c - d (Eq. FD:PoissonDiscrete), d the charge
+ * correction of Eq. Phi:correction with phi off the grid from the multipole
+ * expansion of Eq. phi:BC:discrete, moments Q_lm = h^3 sum |x|^l Y_lm c (real
+ * orthonormal Y_lm).  Preconditioned CG from phi = 0 (use_guess = 0) or from
+ * the values in phi (use_guess = 1) until ||r||_2 <= tol ||c - d||_2 (r the
+ * recursively updated residual) or max_iter iterations.  charge, phi: device
+ * FP64 arrays of N_d values (phi overwritten with the solution); iters,
+ * rel_resid: host outputs (may be NULL); moments: NULL or a host array of
+ * (lmax+1)^2 values receiving Q_lm (index l*l + l + m).  All sums FP64 in a
+ * fixed order (reproducible bit for bit).  Synchronous on stream (it reads a
+ * convergence flag every 8 iterations).  Errors: SPARC_E_ARG (tol <= 0,
+ * max_iter < 0), SPARC_E_WORKSPACE, SPARC_E_ALIAS, SPARC_E_SHAPE, SPARC_E_HIP. */
+int sparc_poisson_solve(sparc_poisson *p, const double *charge, double *phi, int32_t use_guess, double tol,
+                        int32_t max_iter, int32_t *iters, double *rel_resid, double *moments, void *ws,
+                        size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------- CheFSI passes */
 
 /* Workspace bytes of sparc_chefsi (0 on bad arguments). */

@@ -34,6 +34,8 @@ Functions and the passages they follow:
                         (Alg. 4): Y_Jnlm, W_Jnlm and the nonlocal atomic force.
 * ``dense_hamiltonian`` brute-force N_d x N_d matrix for tiny grids.
 * ``cheb_closed_form``  C_m(x) from its trigonometric/hyperbolic definition.
+
+The electrostatic potential solve (Sec. 3.3) lives in ``oracle.poisson``.
 """
 from __future__ import annotations
 

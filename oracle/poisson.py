@@ -134,11 +134,13 @@ def poisson_apply(n: Sequence[int], h: float, no: int, phi: np.ndarray) -> np.nd
     return -laplacian(n, h, no, phi) / FOUR_PI
 
 
-def block_jacobi(n: Sequence[int], h: float, no: int, B: int = 4) -> Callable:
-    """The block-Jacobi preconditioner: the nodes are cut into blocks of B^3
-    (ragged at the high end of each axis), and each block of the residual is
-    multiplied by the inverse of the operator restricted to that block (a
-    dense matrix, the same for every block of one shape)."""
+def block_jacobi(n: Sequence[int], h: float, no: int, B=4) -> Callable:
+    """The block-Jacobi preconditioner: the nodes are cut into blocks of
+    B[0] x B[1] x B[2] nodes (B an int: a cube), ragged at the high end of
+    each axis, and each block of the residual is multiplied by the inverse of
+    the operator restricted to that block (a dense matrix, the same for every
+    block of one shape)."""
+    B = (B, B, B) if np.isscalar(B) else tuple(int(b) for b in B)
     w = fd_weights(no, h)
     inv = {}
 
@@ -159,7 +161,7 @@ def block_jacobi(n: Sequence[int], h: float, no: int, B: int = 4) -> Callable:
                             A[t, u] += w[q]
         return np.linalg.inv(-A / FOUR_PI)
 
-    starts = [list(range(0, n[d], B)) for d in range(3)]
+    starts = [list(range(0, n[d], B[d])) for d in range(3)]
 
     def apply(r: np.ndarray) -> np.ndarray:
         R = np.asarray(r, dtype=np.float64).reshape(tuple(n))
@@ -167,7 +169,8 @@ def block_jacobi(n: Sequence[int], h: float, no: int, B: int = 4) -> Callable:
         for i0 in starts[0]:
             for j0 in starts[1]:
                 for k0 in starts[2]:
-                    sl = (slice(i0, min(i0 + B, n[0])), slice(j0, min(j0 + B, n[1])), slice(k0, min(k0 + B, n[2])))
+                    sl = (slice(i0, min(i0 + B[0], n[0])), slice(j0, min(j0 + B[1], n[1])),
+                          slice(k0, min(k0 + B[2], n[2])))
                     shape = tuple(s.stop - s.start for s in sl)
                     if shape not in inv:
                         inv[shape] = block_matrix(shape)

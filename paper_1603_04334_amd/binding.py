@@ -109,6 +109,10 @@ _SIGS = {
     "sparc_stream_copy": (_i32, [_vp, _vp, _sz, _vp]),
     "sparc_fermi_level": (_i32, [_dp, _i32, _dbl, _dbl, _dp, _dp]),
     "sparc_density": (_i32, [_i32, _vp, _i64, _i64, _i32, _vp, _dbl, _vp, _vp]),
+    "sparc_poisson_create": (_i32, [ctypes.POINTER(sparc_grid), _i32, _vp, ctypes.POINTER(_vp)]),
+    "sparc_poisson_destroy": (_i32, [_vp]),
+    "sparc_poisson_workspace_bytes": (_sz, [_vp]),
+    "sparc_poisson_solve": (_i32, [_vp, _vp, _vp, _i32, _dbl, _i32, ctypes.POINTER(_i32), _dp, _dp, _vp, _sz, _vp]),
     "sparc_force_workspace_bytes": (_sz, [_vp, _i32]),
     "sparc_nonlocal_force": (_i32, [_vp, _i32, _vp, _i64, _i32, _vp, _vp, _vp, _sz, _vp]),
     "sparc_chefsi_workspace_bytes": (_sz, [_vp, _i32, _i32]),
@@ -428,6 +432,53 @@ def rotate(Y, Qt, out=None, ws=None, stream=None):
     check(lib().sparc_rotate(dt, _ptr(Y), ldy, nd, ns, _ptr(Qt), _ptr(out), out.stride(0), _ptr(ws), ws.numel(),
                              _stream(stream)), "sparc_rotate")
     return out
+
+
+class Poisson:
+    """Electrostatic potential solver for one grid (n, h, stencil radius)."""
+
+    def __init__(self, n, h: float, radius: int = 6, lmax: int = 6, block=(4, 4, 4)):
+        g = sparc_grid()
+        g.n[0], g.n[1], g.n[2] = (int(v) for v in n)
+        g.h = float(h)
+        g.radius = int(radius)
+        self.nd = int(n[0]) * int(n[1]) * int(n[2])
+        self.lmax = int(lmax)
+        blk = (_i32 * 3)(*[int(b) for b in block])
+        hd = _vp()
+        check(lib().sparc_poisson_create(ctypes.byref(g), int(lmax), ctypes.cast(blk, _vp), ctypes.byref(hd)),
+              "sparc_poisson_create")
+        self.handle = hd
+
+    def solve(self, charge, phi=None, use_guess: bool = False, tol: float = 1e-10, max_iter: int = 5000, ws=None,
+              stream=None):
+        """Returns (phi, iterations, relative residual, moments Q_lm)."""
+        import torch
+        if charge.dtype != torch.float64 or charge.numel() != self.nd or not charge.is_cuda:
+            raise ValueError("charge must be a device float64 tensor of N_d values")
+        if phi is None:
+            phi = torch.zeros(self.nd, dtype=torch.float64, device=charge.device)
+        if ws is None:
+            ws = torch.empty(int(lib().sparc_poisson_workspace_bytes(self.handle)), dtype=torch.uint8,
+                             device=charge.device)
+        it = _i32()
+        res = ctypes.c_double()
+        mom = np.zeros((self.lmax + 1) ** 2)
+        check(lib().sparc_poisson_solve(self.handle, _ptr(charge), _ptr(phi), 1 if use_guess else 0, float(tol),
+                                        int(max_iter), ctypes.byref(it), ctypes.byref(res), mom.ctypes.data_as(_dp),
+                                        _ptr(ws), ws.numel(), _stream(stream)), "sparc_poisson_solve")
+        return phi, it.value, res.value, mom
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().sparc_poisson_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:
