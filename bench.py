@@ -625,7 +625,7 @@ def main():
     alg = alg_bytes_per_step_launch(case, cl, s)
     achieved = alg / avg_s / 1e9
     copy_gbs = copy_bandwidth()
-    tz, ty, cx, cg = op.step_config(binding.SPARC_F32 if args.dtype == "f32" else binding.SPARC_F64, case.ns)
+    tz, ty, cx, cg, cb = op.step_config(binding.SPARC_F32 if args.dtype == "f32" else binding.SPARC_F64, case.ns)
 
     out = {
         "metric": "filtered orbital*gridpts/s",
@@ -643,7 +643,7 @@ def main():
         "config": {"workload": case.name, "grid": [case.n] * 3, "h": case.h, "atoms": case.natoms,
                    "projectors_per_atom": (case.lmax + 1) ** 2, "orbitals": case.ns, "degree": case.m,
                    "stencil_radius": 6, "step": "lanczos40_fp64+cheb_filter+rayleigh_ritz_fp64+rotation",
-                   "parallelism": "single_gpu", "tile": {"z": tz, "y": ty, "chunk_x": cx, "col_group": cg}},
+                   "parallelism": "single_gpu", "tile": {"z": tz, "y": ty, "chunk_x": cx, "col_group": cg, "col_block": cb}},
         "filter_only": {"value": updates / (main_res["filter_ms"] * 1e-3), "ms": main_res["filter_ms"]},
         "stages_ms": main_res["stages_ms"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -545,18 +545,21 @@ int sparc_profile_reset(void);
  * (tile_z = 32; tile_y 16, 32 or 64 for FP32, 8, 16 or 32 for FP64), the
  * number of x-planes per workgroup (chunk_x <= 0: library choice; rounded up
  * to a multiple of 8) and the column group (col_group <= 0: library choice;
- * that many columns of one patch go to consecutive workgroups, so they share
- * V_eff and the projector values in the L2 cache).  tile_z = tile_y = 0
- * restores the library's patch choice.  Applies to blocks of every width.
- * The x split and the column group never change results; the patch height
- * changes the order in which projections are summed (results then agree to
+ * that many column blocks of one patch go to consecutive workgroups, so they
+ * share V_eff and the projector values in the L2 cache) and the column block
+ * (col_block: columns stepped by one workgroup, 1 or 2, sharing the V_eff
+ * loads; 0: library choice).  tile_z = tile_y = 0 restores the library's
+ * patch choice.  Applies to blocks of every width.  The x split, the column
+ * group and the column block never change results; the patch height changes
+ * the order in which projections are summed (results then agree to
  * rounding).  Not thread-safe against calls that use the op.
- * Errors: SPARC_E_ARG (null op, bad dtype, unsupported tile). */
+ * Errors: SPARC_E_ARG (null op, bad dtype, unsupported tile, col_block
+ * outside 0..2). */
 int sparc_op_set_launch(sparc_op *op, int32_t dtype, int32_t tile_z, int32_t tile_y, int32_t chunk_x,
-                        int32_t col_group);
+                        int32_t col_group, int32_t col_block);
 
-/* Measure the patch heights, a few x splits and column groups of the vector
- * step kernels for this op (its grid, atoms and projectors), dtype and
+/* Measure the patch heights, a few x splits, column groups and column blocks
+ * (1 or 2) of the vector step kernels for this op (its grid, atoms and projectors), dtype and
  * column count on scratch blocks (allocated and freed here), timing the launch
  * a filter step makes (projections in and out), apply the fastest to the op
  * for blocks of ns columns (other widths keep the library's choice), and
@@ -569,15 +572,15 @@ int sparc_op_set_launch(sparc_op *op, int32_t dtype, int32_t tile_z, int32_t til
  * of 4 FP32 / 2 FP64 nodes, or no patch plan is usable: nothing to tune),
  * SPARC_E_NOMEM, SPARC_E_HIP. */
 int sparc_autotune(sparc_op *op, int32_t dtype, int32_t ns, void *stream, int32_t *tile_z, int32_t *tile_y,
-                   int32_t *chunk_x, int32_t *col_group, double *best_us);
+                   int32_t *chunk_x, int32_t *col_group, int32_t *col_block, double *best_us);
 
 /* Launch configuration of the step kernels for a dtype and ns as chosen by
  * the library for the op (out parameters may be NULL).  For grids the vector
- * kernels take: tile_z = 32, tile_y, chunk_x and col_group of the vector
- * launch; otherwise the scalar kernels' patch (32 x 16), x-chunk and
- * col_group = 1. */
+ * kernels take: tile_z = 32, tile_y, chunk_x, col_group and col_block of the
+ * vector launch; otherwise the scalar kernels' patch (32 x 16), x-chunk and
+ * col_group = col_block = 1. */
 int sparc_step_config(const sparc_op *op, int32_t dtype, int32_t ns, int32_t *tile_z, int32_t *tile_y,
-                      int32_t *chunk_x, int32_t *col_group);
+                      int32_t *chunk_x, int32_t *col_group, int32_t *col_block);
 
 #ifdef __cplusplus
 }

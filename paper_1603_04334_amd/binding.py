@@ -124,9 +124,9 @@ _SIGS = {
     "sparc_profile_enable": (_i32, [_i32]),
     "sparc_profile_read": (_i32, [_i32, ctypes.POINTER(_i64), _dp]),
     "sparc_profile_reset": (_i32, []),
-    "sparc_op_set_launch": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32]),
+    "sparc_op_set_launch": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _i32]),
     "sparc_autotune": (_i32, [_vp, _i32, _i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
-                              ctypes.POINTER(_i32), _dp]),
+                              ctypes.POINTER(_i32), ctypes.POINTER(_i32), _dp]),
     "sparc_rotate_workspace_bytes": (ctypes.c_size_t, [_i32, _i32]),
     "sparc_server_create": (_i32, [ctypes.POINTER(sparc_server_cfg), ctypes.POINTER(_vp)]),
     "sparc_filter_submit": (_i32, [_vp, ctypes.POINTER(sparc_filter_job), ctypes.POINTER(ctypes.c_uint64)]),
@@ -143,7 +143,7 @@ _SIGS = {
     "sparc_batch_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "sparc_batch_destroy": (_i32, [_vp]),
     "sparc_step_config": (_i32, [_vp, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
-                                 ctypes.POINTER(_i32)]),
+                                 ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
 }
 
 
@@ -352,24 +352,26 @@ class Operator:
                                  _ptr(ws), ws.numel(), _stream(stream)), "sparc_chefsi")
         return theta, lf, deg
 
-    def set_launch(self, dtype_code: int, tile_z: int = 0, tile_y: int = 0, chunk_x: int = 0, col_group: int = 0):
-        check(lib().sparc_op_set_launch(self.handle, dtype_code, tile_z, tile_y, chunk_x, col_group),
+    def set_launch(self, dtype_code: int, tile_z: int = 0, tile_y: int = 0, chunk_x: int = 0, col_group: int = 0,
+                   col_block: int = 0):
+        check(lib().sparc_op_set_launch(self.handle, dtype_code, tile_z, tile_y, chunk_x, col_group, col_block),
               "sparc_op_set_launch")
 
     def autotune(self, dtype_code: int, ns: int, stream=None):
-        """(tile_z, tile_y, chunk_x, col_group, microseconds per step)"""
-        tz, ty, cx, cg = _i32(), _i32(), _i32(), _i32()
+        """(tile_z, tile_y, chunk_x, col_group, col_block, microseconds per step)"""
+        tz, ty, cx, cg, cb = _i32(), _i32(), _i32(), _i32(), _i32()
         us = ctypes.c_double()
         check(lib().sparc_autotune(self.handle, dtype_code, ns, _stream(stream), ctypes.byref(tz), ctypes.byref(ty),
-                                   ctypes.byref(cx), ctypes.byref(cg), ctypes.byref(us)), "sparc_autotune")
-        return tz.value, ty.value, cx.value, cg.value, us.value
+                                   ctypes.byref(cx), ctypes.byref(cg), ctypes.byref(cb), ctypes.byref(us)),
+              "sparc_autotune")
+        return tz.value, ty.value, cx.value, cg.value, cb.value, us.value
 
     def step_config(self, dtype_code: int, ns: int):
-        """(tile_z, tile_y, chunk_x, col_group)"""
-        tz, ty, cx, cg = _i32(), _i32(), _i32(), _i32()
+        """(tile_z, tile_y, chunk_x, col_group, col_block)"""
+        tz, ty, cx, cg, cb = _i32(), _i32(), _i32(), _i32(), _i32()
         check(lib().sparc_step_config(self.handle, dtype_code, ns, ctypes.byref(tz), ctypes.byref(ty),
-                                      ctypes.byref(cx), ctypes.byref(cg)), "sparc_step_config")
-        return tz.value, ty.value, cx.value, cg.value
+                                      ctypes.byref(cx), ctypes.byref(cg), ctypes.byref(cb)), "sparc_step_config")
+        return tz.value, ty.value, cx.value, cg.value, cb.value
 
 
 def stream_copy(dst, src, stream=None):

@@ -407,9 +407,10 @@ size_t sparc_workspace_bytes(const sparc_op *op, int32_t dtype, int32_t ns, int3
 }
 
 int sparc_op_set_launch(sparc_op *op, int32_t dtype, int32_t tile_z, int32_t tile_y, int32_t chunk_x,
-                        int32_t col_group)
+                        int32_t col_group, int32_t col_block)
 {
     if (!op || (dtype != SPARC_F64 && dtype != SPARC_F32)) return fail(SPARC_E_ARG, "null op or bad dtype");
+    if (col_block < 0 || col_block > 2) return fail(SPARC_E_ARG, "col_block must be 0, 1 or 2");
     if (tile_z <= 0 && tile_y <= 0) {
         op->tune_shape[dtype] = -1;
     } else {
@@ -422,12 +423,13 @@ int sparc_op_set_launch(sparc_op *op, int32_t dtype, int32_t tile_z, int32_t til
     }
     op->tune_chunk[dtype] = chunk_x > 0 ? chunk_x : 0;
     op->tune_group[dtype] = col_group > 0 ? col_group : 0;
+    op->tune_cblk[dtype] = col_block;
     op->tune_ns[dtype] = -1;
     return SPARC_OK;
 }
 
 int sparc_step_config(const sparc_op *op, int32_t dtype, int32_t ns, int32_t *tile_z, int32_t *tile_y,
-                      int32_t *chunk_x, int32_t *col_group)
+                      int32_t *chunk_x, int32_t *col_group, int32_t *col_block)
 {
     if (!op || ns < 1 || (dtype != SPARC_F64 && dtype != SPARC_F32)) return fail(SPARC_E_ARG, "null op, ns < 1 or bad dtype");
     const FLaunch V = choose_vec_launch(op, dtype, ns, {});
@@ -435,7 +437,8 @@ int sparc_step_config(const sparc_op *op, int32_t dtype, int32_t ns, int32_t *ti
         if (tile_z) *tile_z = 32;
         if (tile_y) *tile_y = kPlanTY[V.plan];
         if (chunk_x) *chunk_x = V.chunk_x;
-        if (col_group) *col_group = std::min(V.cgroup, ns);
+        if (col_group) *col_group = std::min(V.cgroup, (ns + V.cblk - 1) / V.cblk);
+        if (col_block) *col_block = V.cblk;
         return SPARC_OK;
     }
     StepLaunch L = choose_step_launch(op, dtype, ns);
@@ -443,6 +446,7 @@ int sparc_step_config(const sparc_op *op, int32_t dtype, int32_t ns, int32_t *ti
     if (tile_y) *tile_y = kShapes[L.shape].ty();
     if (chunk_x) *chunk_x = L.chunk_x;
     if (col_group) *col_group = 1;
+    if (col_block) *col_block = 1;
     return SPARC_OK;
 }
 

@@ -30,6 +30,9 @@
 //    on the same XCD and share halos in its L2 (optionally, col_group columns
 //    of one patch run back to back and share V_eff); yprev and out are streamed
 //    non-temporally when a step's blocks exceed the last-level cache.
+//  * Orbital blocking (col_block = 2): one workgroup steps two columns of the
+//    same patch, loading V_eff once for both and sharing the halo offsets and
+//    the plane loop; each column keeps its own register queue and LDS plane.
 #include <algorithm>
 #include <cstring>
 #include <type_traits>
@@ -83,6 +86,7 @@ FLaunch choose_vec_launch(const sparc_op *op, int dtype, int ns, std::initialize
     L.plan = plan;
     set_chunks(op, nch, L);
     L.cgroup = (tuned && op->tune_group[dtype] > 0) ? op->tune_group[dtype] : 1;
+    L.cblk = (tuned && op->tune_cblk[dtype] == 2) ? 2 : 1;
     return L;
 }
 
@@ -117,8 +121,10 @@ static int launch_fstep_t(const sparc_op *op, const FLaunch &L, const void *yk, 
     a.tiles_z = (op->n[2] + kFTZ - 1) / kFTZ;
     a.chunk_x = L.chunk_x;
     a.nchunks = L.nchunks;
-    const int G = std::max(1, std::min(L.cgroup, ns));
-    const long long nb = (long long)(ns + G - 1) / G * G * L.nchunks * a.tiles_y * a.tiles_z;
+    const int cb = L.cblk == 2 ? 2 : 1;
+    const int ngroups = (ns + cb - 1) / cb;  // column blocks
+    const int G = std::max(1, std::min(L.cgroup, ngroups));
+    const long long nb = (long long)(ngroups + G - 1) / G * G * L.nchunks * a.tiles_y * a.tiles_z;
     if (nb > 0x7fffffffLL) return fail(SPARC_E_SHAPE, "too many workgroups for one launch");
     a.nblocks = (int)nb;
     a.remap = 1;
@@ -163,15 +169,15 @@ static int launch_fstep_t(const sparc_op *op, const FLaunch &L, const void *yk, 
     const int natoms = std::max(op->natoms, 1);
     if constexpr (std::is_same<T, float>::value) {
         switch (ty) {
-            case 16: return fstep_f32_ty16(a, g, natoms, ncb, nitems, ngb, prev, strm, stream);
-            case 32: return fstep_f32_ty32(a, g, natoms, ncb, nitems, ngb, prev, strm, stream);
-            case 64: return fstep_f32_ty64(a, g, natoms, ncb, nitems, ngb, prev, strm, stream);
+            case 16: return fstep_f32_ty16(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
+            case 32: return fstep_f32_ty32(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
+            case 64: return fstep_f32_ty64(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
         }
     } else {
         switch (ty) {
-            case 8: return fstep_f64_ty8(a, g, natoms, ncb, nitems, ngb, prev, strm, stream);
-            case 16: return fstep_f64_ty16(a, g, natoms, ncb, nitems, ngb, prev, strm, stream);
-            case 32: return fstep_f64_ty32(a, g, natoms, ncb, nitems, ngb, prev, strm, stream);
+            case 8: return fstep_f64_ty8(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
+            case 16: return fstep_f64_ty16(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
+            case 32: return fstep_f64_ty32(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
         }
     }
     return fail(SPARC_E_ARG, "patch height not available for this dtype");

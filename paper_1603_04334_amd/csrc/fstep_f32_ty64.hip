@@ -4,9 +4,9 @@
 namespace sparc {
 
 int fstep_f32_ty64(const FStepArgs<float> &a, const GatherArgs<float, float> &g, int natoms, int ncb, int nitems, int ngb,
-                    bool prev, bool strm, hipStream_t s)
+                    bool prev, bool strm, int cblk, hipStream_t s)
 {
-    return fstep_dispatch<float, 64>(a, g, natoms, ncb, nitems, ngb, prev, strm, s);
+    return fstep_dispatch<float, 64>(a, g, natoms, ncb, nitems, ngb, prev, strm, cblk, s);
 }
 
 }  // namespace sparc

@@ -54,7 +54,9 @@ struct FStepArgs {
     T alpha, beta, shift;
 };
 
-template <typename T, int TY, bool PREV, bool STREAM>
+// B: columns per workgroup.  With B = 2 the two columns of one patch share
+// the V_eff loads, the halo offsets and the plane loop (orbital blocking).
+template <typename T, int TY, bool PREV, bool STREAM, int B = 1>
 struct FStep {
     static constexpr int R = kMaxRadius;
     static constexpr int VZ = VecTraits<T>::N;
@@ -72,27 +74,31 @@ struct FStep {
     static constexpr int NH = (NHALO + NT - 1) / NT;
     static constexpr int WU = 2 * ZU + 1;  // units of a lane's z window
     static_assert(NT % 64 == 0, "whole waves");
+    static_assert(B == 1 || B == 2, "one or two columns per workgroup");
 
     struct Shared {
-        T plane[2][SY * SZ];
+        T plane[2][B][SY * SZ];
     };
 
     const FStepArgs<T> &a;
-    const T *yk;
-    const T *yp;
-    T *out;
+    const T *yk[B];
+    const T *yp[B];
+    T *out[B];
     long long P;
     int col, chunk, xs, xe, ly, lz, y, zg;
     unsigned pofs;      // in-plane byte offset of the lane's unit, or kOutside
+    unsigned sofs[B];   // store offset per column (kOutside for a column past the block)
     unsigned hofs[NH];  // halo units: in-plane byte offsets, or kOutside
     int hl[NH];         // halo units: LDS element index, or -1
-    V q[QL];  // the lane's unit at planes x-R .. x+R (one vector per plane)
+    V q[B][QL];  // per column, the lane's unit at planes x-R .. x+R (one vector per plane)
     // the two load stages (values for one plane: its halo, the queue head at
     // plane t+R, V_eff and yprev at the lane's unit), one named member per
-    // stage and only whole-vector accesses, so that they stay in registers
+    // stage and only whole-vector accesses at constant indices, so that they
+    // stay in registers
     struct Stage {
-        V h[NH];
-        V qh, v, p;
+        V h[B][NH];
+        V qh[B], p[B];
+        V v;
     };
     Stage st0, st1;
     template <int S>
@@ -113,74 +119,82 @@ struct FStep {
     __device__ __forceinline__ void load_stage(int t)
     {
         Stage &s = stage<S>();
-        const auto rk = plane_rsrc(yk, t, a.n1, P);
 #pragma unroll
-        for (int i = 0; i < NH; ++i) s.h[i] = vload<T, 0>(rk, hofs[i]);
-        s.qh = vload<T, 0>(plane_rsrc(yk, t + R, a.n1, P), pofs);
+        for (int b = 0; b < B; ++b) {
+            const auto rk = plane_rsrc(yk[b], t, a.n1, P);
+#pragma unroll
+            for (int i = 0; i < NH; ++i) s.h[b][i] = vload<T, 0>(rk, hofs[i]);
+            s.qh[b] = vload<T, 0>(plane_rsrc(yk[b], t + R, a.n1, P), pofs);
+        }
         s.v = vload<T, 0>(plane_rsrc(a.veff, t, a.n1, P), pofs);
-        if constexpr (PREV) s.p = vload<T, STREAM ? kNonTemporal : 0>(plane_rsrc(yp, t, a.n1, P), pofs);
+        if constexpr (PREV) {
+#pragma unroll
+            for (int b = 0; b < B; ++b) s.p[b] = vload<T, STREAM ? kNonTemporal : 0>(plane_rsrc(yp[b], t, a.n1, P), pofs);
+        }
     }
 
     template <int S, int Q>
     __device__ __forceinline__ void plane(int x, Shared &sh)
     {
-        T *L = sh.plane[S];
-        q[slot<Q>(2 * R)] = stage<S>().qh;
-        // publish the centre plane and its halo
-        const V cen = q[slot<Q>(R)];
-        *(V *)&L[(R + ly) * SZ + PADZ + VZ * lz] = cen;
+        // publish the centre plane and its halo of every column
 #pragma unroll
-        for (int i = 0; i < NH; ++i)
-            if (hl[i] >= 0) *(V *)&L[hl[i]] = stage<S>().h[i];
+        for (int b = 0; b < B; ++b) {
+            T *L = sh.plane[S][b];
+            q[b][slot<Q>(2 * R)] = stage<S>().qh[b];
+            *(V *)&L[(R + ly) * SZ + PADZ + VZ * lz] = q[b][slot<Q>(R)];
+#pragma unroll
+            for (int i = 0; i < NH; ++i)
+                if (hl[i] >= 0) *(V *)&L[hl[i]] = stage<S>().h[b][i];
+        }
         __syncthreads();
 
         const V vv = stage<S>().v;
-        V pv;
-        if constexpr (PREV) pv = stage<S>().p;
-        T vcur[VZ], pcur[VZ];
+        V pv[B];
 #pragma unroll
-        for (int j = 0; j < VZ; ++j) {
-            vcur[j] = vv[j];
-            pcur[j] = PREV ? pv[j] : T(0);
-        }
+        for (int b = 0; b < B; ++b) pv[b] = PREV ? stage<S>().p[b] : V{};
         // request plane x+2 into the stage just consumed
         load_stage<S>(x + 2);
 
-        // z window: PADZ values on each side of the lane's unit
-        T w[WU * VZ];
-        const T *row = &L[(R + ly) * SZ + VZ * lz];
 #pragma unroll
-        for (int u = 0; u < WU; ++u) {
-            const V t = *(const V *)&row[u * VZ];
+        for (int b = 0; b < B; ++b) {
+            const T *L = sh.plane[S][b];
+            const V cen = q[b][slot<Q>(R)];
+            // z window: PADZ values on each side of the lane's unit
+            T w[WU * VZ];
+            const T *row = &L[(R + ly) * SZ + VZ * lz];
 #pragma unroll
-            for (int j = 0; j < VZ; ++j) w[u * VZ + j] = t[j];
-        }
-        T acc[VZ];
+            for (int u = 0; u < WU; ++u) {
+                const V t = *(const V *)&row[u * VZ];
 #pragma unroll
-        for (int j = 0; j < VZ; ++j) acc[j] = a.c0 * cen[j];
+                for (int j = 0; j < VZ; ++j) w[u * VZ + j] = t[j];
+            }
+            T acc[VZ];
 #pragma unroll
-        for (int p = 1; p <= R; ++p) {
-            const V ym = *(const V *)&L[(R + ly - p) * SZ + PADZ + VZ * lz];
-            const V yq = *(const V *)&L[(R + ly + p) * SZ + PADZ + VZ * lz];
+            for (int j = 0; j < VZ; ++j) acc[j] = a.c0 * cen[j];
+#pragma unroll
+            for (int p = 1; p <= R; ++p) {
+                const V ym = *(const V *)&L[(R + ly - p) * SZ + PADZ + VZ * lz];
+                const V yq = *(const V *)&L[(R + ly + p) * SZ + PADZ + VZ * lz];
+#pragma unroll
+                for (int j = 0; j < VZ; ++j) {
+                    const T six = (q[b][slot<Q>(R - p)][j] + q[b][slot<Q>(R + p)][j]) + (ym[j] + yq[j]) +
+                                  (w[PADZ + j - p] + w[PADZ + j + p]);
+                    acc[j] += a.cp[p - 1] * six;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < VZ; ++j) acc[j] += (vv[j] - a.shift) * cen[j];
+
+            V rv;
 #pragma unroll
             for (int j = 0; j < VZ; ++j) {
-                const T six = (q[slot<Q>(R - p)][j] + q[slot<Q>(R + p)][j]) + (ym[j] + yq[j]) +
-                              (w[PADZ + j - p] + w[PADZ + j + p]);
-                acc[j] += a.cp[p - 1] * six;
+                T r = a.alpha * acc[j];
+                if constexpr (PREV) r -= a.beta * pv[b][j];
+                rv[j] = r;
             }
+            // written once; units outside the grid are dropped by the range check
+            vstore<T, STREAM ? kNonTemporal : 0>(rv, plane_rsrc((const T *)out[b], x, a.n1, P), sofs[b]);
         }
-#pragma unroll
-        for (int j = 0; j < VZ; ++j) acc[j] += (vcur[j] - a.shift) * cen[j];
-
-        V rv;
-#pragma unroll
-        for (int j = 0; j < VZ; ++j) {
-            T r = a.alpha * acc[j];
-            if constexpr (PREV) r -= a.beta * pcur[j];
-            rv[j] = r;
-        }
-        // written once; units outside the grid are dropped by the range check
-        vstore<T, STREAM ? kNonTemporal : 0>(rv, plane_rsrc((const T *)out, x, a.n1, P), pofs);
     }
 
     template <int U>
@@ -194,13 +208,13 @@ struct FStep {
     }
 
     // b: workgroup index within the launch (or work item within a batch)
-    __device__ __forceinline__ void run(int b, Shared &sh)
+    __device__ __forceinline__ void run(int wg, Shared &sh)
     {
         const int nb = a.nblocks;
-        const int xcd = b & 7;
-        int t = a.remap ? xcd * (nb >> 3) + min(xcd, nb & 7) + (b >> 3) : b;
+        const int xcd = wg & 7;
+        int t = a.remap ? xcd * (nb >> 3) + min(xcd, nb & 7) + (wg >> 3) : wg;
         // cgroup consecutive indices are the same patch of consecutive
-        // columns, so they share the patch's V_eff in L2
+        // column blocks, so they share the patch's V_eff in L2
         const int cg = t % a.cgroup;
         t /= a.cgroup;
         const int tzi = t % a.tiles_z;
@@ -208,7 +222,7 @@ struct FStep {
         const int tyi = t % a.tiles_y;
         t /= a.tiles_y;
         chunk = t % a.nchunks;
-        col = (t / a.nchunks) * a.cgroup + cg;
+        col = ((t / a.nchunks) * a.cgroup + cg) * B;
         if (col >= a.ns) return;  // the padding of the last column group
 
         const int tid = threadIdx.x;
@@ -218,11 +232,17 @@ struct FStep {
         y = y0 + ly;
         zg = z0 + VZ * lz;
         P = (long long)a.n2 * a.n3;
-        yk = a.yk + (size_t)col * a.ldk;
-        yp = PREV ? a.yprev + (size_t)col * a.ldp : nullptr;
-        out = a.out + (size_t)col * a.ldo;
         const bool own_ok = (zg < a.n3) && (y < a.n2);
         pofs = own_ok ? (unsigned)(y * a.n3 + zg) * (unsigned)sizeof(T) : kOutside;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            // a column past the block repeats the last one and stores nothing
+            const int c = min(col + b, a.ns - 1);
+            yk[b] = a.yk + (size_t)c * a.ldk;
+            yp[b] = PREV ? a.yprev + (size_t)c * a.ldp : nullptr;
+            out[b] = a.out + (size_t)c * a.ldo;
+            sofs[b] = col + b < a.ns ? pofs : kOutside;
+        }
         xs = chunk * a.chunk_x;
         xe = min(a.n1, xs + a.chunk_x);
 
@@ -253,7 +273,9 @@ struct FStep {
 
         // queue: planes xs-R .. xs+R-1 (heads are filled from the stages)
 #pragma unroll
-        for (int d = 0; d < 2 * R; ++d) q[d] = vload<T, 0>(plane_rsrc(yk, xs - R + d, a.n1, P), pofs);
+        for (int b = 0; b < B; ++b)
+#pragma unroll
+            for (int d = 0; d < 2 * R; ++d) q[b][d] = vload<T, 0>(plane_rsrc(yk[b], xs - R + d, a.n1, P), pofs);
         load_stage<0>(xs);
         load_stage<1>(xs + 1);
         for (int x0 = xs; x0 < xe; x0 += 2 * QL) run_block<0>(x0, xe, sh);

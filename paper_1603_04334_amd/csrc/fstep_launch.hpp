@@ -12,7 +12,7 @@ namespace sparc {
 // ngb run NT/256 projector-gather items of yk each (item = atom + natoms *
 // (column block + ncb * split), 256 threads apiece; a group past the last
 // item only joins the item's barrier), filling CUs as the step drains.
-template <typename T, int TY, bool PREV, bool STREAM, bool TAIL>
+template <typename T, int TY, bool PREV, bool STREAM, bool TAIL, int B>
 __global__ void __launch_bounds__((kFTZ / VecTraits<T>::N) * TY)
     fstep_kernel(const FStepArgs<T> a, const GatherArgs<T, T> g, int natoms, int ncb, int nitems)
 {
@@ -31,19 +31,20 @@ __global__ void __launch_bounds__((kFTZ / VecTraits<T>::N) * TY)
             return;
         }
     }
-    using K = FStep<T, TY, PREV, STREAM>;
+    using K = FStep<T, TY, PREV, STREAM, B>;
     __shared__ __align__(16) typename K::Shared sh;
     K k(a);
     k.run(blockIdx.x, sh);
 }
 
-template <typename T, int TY>
-int fstep_dispatch(const FStepArgs<T> &a, const GatherArgs<T, T> &g, int natoms, int ncb, int nitems, int ngb,
-                   bool prev, bool strm, hipStream_t s)
+template <typename T, int TY, int B>
+int fstep_dispatch_b(const FStepArgs<T> &a, const GatherArgs<T, T> &g, int natoms, int ncb, int nitems, int ngb,
+                     bool prev, bool strm, hipStream_t s)
 {
     constexpr int NT = (kFTZ / VecTraits<T>::N) * TY;
     const dim3 grid(a.nblocks + ngb), b(NT);
-#define SPARC_FS(P, S, G) hipLaunchKernelGGL((fstep_kernel<T, TY, P, S, G>), grid, b, 0, s, a, g, natoms, ncb, nitems)
+#define SPARC_FS(P, S, G) \
+    hipLaunchKernelGGL((fstep_kernel<T, TY, P, S, G, B>), grid, b, 0, s, a, g, natoms, ncb, nitems)
     // patches of fewer than 256 threads cannot host a gather item
     if (ngb > 0 && NT < 256) return fail(SPARC_E_ARG, "gather tail needs 256-thread workgroups");
     if constexpr (NT < 256) {
@@ -79,9 +80,18 @@ int fstep_dispatch(const FStepArgs<T> &a, const GatherArgs<T, T> &g, int natoms,
     return SPARC_OK;
 }
 
+// cblk: columns per workgroup (1 or 2)
+template <typename T, int TY>
+int fstep_dispatch(const FStepArgs<T> &a, const GatherArgs<T, T> &g, int natoms, int ncb, int nitems, int ngb,
+                   bool prev, bool strm, int cblk, hipStream_t s)
+{
+    if (cblk == 2) return fstep_dispatch_b<T, TY, 2>(a, g, natoms, ncb, nitems, ngb, prev, strm, s);
+    return fstep_dispatch_b<T, TY, 1>(a, g, natoms, ncb, nitems, ngb, prev, strm, s);
+}
+
 // per (type, patch height) launches, one translation unit each
 #define SPARC_FSTEP_DECL(name, T) \
-    int name(const FStepArgs<T> &, const GatherArgs<T, T> &, int, int, int, int, bool, bool, hipStream_t);
+    int name(const FStepArgs<T> &, const GatherArgs<T, T> &, int, int, int, int, bool, bool, int, hipStream_t);
 SPARC_FSTEP_DECL(fstep_f32_ty16, float)
 SPARC_FSTEP_DECL(fstep_f32_ty32, float)
 SPARC_FSTEP_DECL(fstep_f32_ty64, float)

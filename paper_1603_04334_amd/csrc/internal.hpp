@@ -85,6 +85,7 @@ struct sparc_op {
     int tune_chunk[2] = {0, 0};
     int tune_ns[2] = {-1, -1};  // block width the launch choice was tuned for; -1: every width
     int tune_group[2] = {0, 0};  // column group of the vector step (0 = library choice)
+    int tune_cblk[2] = {0, 0};   // columns per workgroup of the vector step (0 = library choice)
     // nonlocal-force tables, built on the first sparc_nonlocal_force call:
     // per atom four gather records (the cube with chi, and for each axis d
     // the cube widened by the stencil radius along d with -grad_d chi), their
@@ -144,7 +145,8 @@ inline size_t gather_bytes(const sparc_op *op, int dtype, int ns)
 struct FLaunch {
     int plan = -1;
     int chunk_x = 0, nchunks = 0;
-    int cgroup = 1;  // columns of one patch on consecutive workgroups
+    int cgroup = 1;  // column blocks of one patch on consecutive workgroups
+    int cblk = 1;    // columns per workgroup (1 or 2: orbital blocking)
 };
 constexpr int kMaxChunks = 16;  // most x-chunks of a vector step launch
 

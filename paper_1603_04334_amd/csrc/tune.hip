@@ -1,12 +1,13 @@
 // Autotuner of the vector step launch: for one operator, dtype and column
-// count it times every patch height, a few x splits and column groups of what
-// a filter step enqueues (the fused stencil / potential / recurrence pass with
-// the projector gather of its input in the same launch, then the projector
-// scatter) on scratch blocks, with HIP events around repeated steps, and keeps
-// the fastest.  Choices are cached per
+// count it times every patch height, a few x splits, column groups and one or
+// two columns per workgroup (orbital blocking) of what a filter step enqueues
+// (the fused stencil / potential / recurrence pass with the projector gather
+// of its input in the same launch, then the projector scatter) on
+// pseudo-random scratch blocks, with HIP events around repeated steps, and
+// keeps the fastest.  Choices are cached per
 // (grid, atoms, projectors, columns, dtype) in the process and, when
 // SPARC_TUNE_CACHE names a file, in that text file (one line per entry:
-// n1 n2 n3 natoms nproj ns dtype plan chunk group microseconds).
+// n1 n2 n3 natoms nproj ns dtype plan chunk group block microseconds).
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -19,7 +20,7 @@ namespace {
 
 using Key = std::tuple<int, int, int, int, int, int, int>;
 struct Choice {
-    int plan, chunk, group;
+    int plan, chunk, group, cblk;
     double us;
 };
 std::mutex g_tune_mu;
@@ -34,10 +35,12 @@ void load_cache()
     if (!path) return;
     FILE *f = std::fopen(path, "r");
     if (!f) return;
-    int n1, n2, n3, na, np, ns, dt, pl, ch, gr;
+    int n1, n2, n3, na, np, ns, dt, pl, ch, gr, cb;
     double us;
-    while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %lf", &n1, &n2, &n3, &na, &np, &ns, &dt, &pl, &ch, &gr, &us) == 11)
-        if (pl >= 0 && pl < kNumPlans && ch > 0 && gr > 0) g_tune[Key(n1, n2, n3, na, np, ns, dt)] = {pl, ch, gr, us};
+    while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %d %lf", &n1, &n2, &n3, &na, &np, &ns, &dt, &pl, &ch, &gr, &cb,
+                       &us) == 12)
+        if (pl >= 0 && pl < kNumPlans && ch > 0 && gr > 0 && (cb == 1 || cb == 2))
+            g_tune[Key(n1, n2, n3, na, np, ns, dt)] = {pl, ch, gr, cb, us};
     std::fclose(f);
 }
 
@@ -47,9 +50,30 @@ void store_cache(const Key &k, const Choice &c)
     if (!path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %.3f\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
-                 std::get<3>(k), std::get<4>(k), std::get<5>(k), std::get<6>(k), c.plan, c.chunk, c.group, c.us);
+    std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d %.3f\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+                 std::get<3>(k), std::get<4>(k), std::get<5>(k), std::get<6>(k), c.plan, c.chunk, c.group, c.cblk,
+                 c.us);
     std::fclose(f);
+}
+
+// scratch blocks of pseudo-random values in [-1, 1) (a multiplicative hash of
+// the index): all-zero blocks run measurably faster than orbital data on this
+// chip, which would bias the choice
+template <typename T>
+__global__ void __launch_bounds__(256) fill_hash(T *__restrict__ x, long long n, unsigned salt)
+{
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        const unsigned h = ((unsigned)i ^ salt) * 2654435761u;
+        x[i] = (T)((double)(h >> 8) * (1.0 / 8388608.0) - 1.0);
+    }
+}
+
+void fill_scratch(int dtype, void *p, size_t bytes, unsigned salt, hipStream_t s)
+{
+    if (dtype == SPARC_F64)
+        hipLaunchKernelGGL(fill_hash<double>, dim3(4096), dim3(256), 0, s, (double *)p, (long long)(bytes / 8), salt);
+    else
+        hipLaunchKernelGGL(fill_hash<float>, dim3(4096), dim3(256), 0, s, (float *)p, (long long)(bytes / 4), salt);
 }
 
 }  // namespace
@@ -58,14 +82,14 @@ void store_cache(const Key &k, const Choice &c)
 using namespace sparc;
 
 extern "C" int sparc_autotune(sparc_op *op, int32_t dtype, int32_t ns, void *stream, int32_t *tile_z, int32_t *tile_y,
-                              int32_t *chunk_x, int32_t *col_group, double *best_us)
+                              int32_t *chunk_x, int32_t *col_group, int32_t *col_block, double *best_us)
 {
     if (!op || ns < 1 || (dtype != SPARC_F64 && dtype != SPARC_F32)) return fail(SPARC_E_ARG, "bad arguments");
     hipStream_t s = (hipStream_t)stream;
     if (choose_vec_launch(op, dtype, ns, {}).plan < 0)
         return fail(SPARC_E_SHAPE, "the vector step kernels cannot take this grid (nothing to tune)");
     const Key key(op->n[0], op->n[1], op->n[2], op->natoms, op->nproj_total, ns, dtype);
-    Choice best{-1, 0, 1, 1e30};
+    Choice best{-1, 0, 1, 1, 1e30};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         load_cache();
@@ -77,6 +101,7 @@ extern "C" int sparc_autotune(sparc_op *op, int32_t dtype, int32_t ns, void *str
         const size_t blk = (size_t)op->nd * ns * es;
         const int saved_shape = op->tune_shape[dtype], saved_chunk = op->tune_chunk[dtype];
         const int saved_ns = op->tune_ns[dtype], saved_group = op->tune_group[dtype];
+        const int saved_cblk = op->tune_cblk[dtype];
         const int lo = dtype == SPARC_F64 ? 0 : 1;
         const int n1 = op->n[0];
         const int chunks[] = {0, n1, (n1 + 1) / 2, (n1 + 3) / 4, (n1 + 7) / 8};
@@ -91,8 +116,8 @@ extern "C" int sparc_autotune(sparc_op *op, int32_t dtype, int32_t ns, void *str
             return fail(SPARC_E_NOMEM, "autotune scratch allocation failed");
         }
         op->tune_ns[dtype] = ns;
-        (void)hipMemsetAsync(X, 0, blk, s);
-        (void)hipMemsetAsync(Pv, 0, blk, s);
+        fill_scratch(dtype, X, blk, 0x9e3779b9u, s);
+        fill_scratch(dtype, Pv, blk, 0x7f4a7c15u, s);
         (void)hipMemsetAsync(G, 0, pb, s);
         hipEvent_t e0, e1;
         (void)hipEventCreate(&e0);
@@ -104,11 +129,14 @@ extern "C" int sparc_autotune(sparc_op *op, int32_t dtype, int32_t ns, void *str
         for (int p = lo; p < lo + 3 && st == SPARC_OK; ++p) {
             for (int ci = 0; ci < 5 && st == SPARC_OK; ++ci) {
                 if (chunks[ci] > 0 && chunks[ci] < 4) continue;
+                for (int cb = 1; cb <= 2 && st == SPARC_OK; ++cb) {
                 for (int gi = 0; gi < 4 && st == SPARC_OK; ++gi) {
-                    if (groups[gi] > ns && gi > 0) continue;
+                    if (groups[gi] * cb > ns && gi > 0) continue;
+                    if (cb == 2 && ns < 2) continue;
                     op->tune_shape[dtype] = p;
                     op->tune_chunk[dtype] = chunks[ci];
                     op->tune_group[dtype] = groups[gi];
+                    op->tune_cblk[dtype] = cb;
                     const FLaunch L = choose_vec_launch(op, dtype, ns, {});
                     if (L.plan != p) continue;
                     // a filter step as the filter runs it: the step with the
@@ -123,7 +151,8 @@ extern "C" int sparc_autotune(sparc_op *op, int32_t dtype, int32_t ns, void *str
                     float ms = 0;
                     (void)hipEventElapsedTime(&ms, e0, e1);
                     const double us = ms * 1e3 / reps;
-                    if (st == SPARC_OK && us < best.us) best = {p, L.chunk_x, L.cgroup, us};
+                    if (st == SPARC_OK && us < best.us) best = {p, L.chunk_x, L.cgroup, L.cblk, us};
+                }
                 }
             }
         }
@@ -131,6 +160,7 @@ extern "C" int sparc_autotune(sparc_op *op, int32_t dtype, int32_t ns, void *str
         op->tune_chunk[dtype] = saved_chunk;
         op->tune_ns[dtype] = saved_ns;
         op->tune_group[dtype] = saved_group;
+        op->tune_cblk[dtype] = saved_cblk;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         (void)hipFree(X);
@@ -146,11 +176,13 @@ extern "C" int sparc_autotune(sparc_op *op, int32_t dtype, int32_t ns, void *str
     op->tune_shape[dtype] = best.plan;
     op->tune_chunk[dtype] = best.chunk;
     op->tune_group[dtype] = best.group;
+    op->tune_cblk[dtype] = best.cblk;
     op->tune_ns[dtype] = ns;  // the choice holds for this block width only
     if (tile_z) *tile_z = 32;
     if (tile_y) *tile_y = kPlanTY[best.plan];
     if (chunk_x) *chunk_x = best.chunk;
     if (col_group) *col_group = best.group;
+    if (col_block) *col_block = best.cblk;
     if (best_us) *best_us = best.us;
     return SPARC_OK;
 }

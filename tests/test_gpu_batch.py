@@ -82,8 +82,10 @@ def test_batch_against_oracle_sampled():
 
 
 def test_autotune_and_launch_choices():
-    """The autotuner picks a patch height and an x split of the vector step.
-    The x split and the column group never change a bit (the projection
+    """The autotuner picks a patch height, an x split, a column group and a
+    column block of the vector step.  The x split, the column group and the
+    column block (one or two columns per workgroup; with 5 columns the last
+    pair is cut short) never change a bit (the projection
     partials are kept per x-segment, whatever the split); another patch height
     sums the partials in another order, so results then agree to rounding."""
     from paper_1603_04334_amd import binding
@@ -95,20 +97,22 @@ def test_autotune_and_launch_choices():
     bounds = (-3.0, 1.5, oracle.upper_bound(cl))
     ref = op.cheb_filter(Xd, 9, *bounds)
     assert op.step_config(binding.SPARC_F32, 5)[:2] == (32, 32)
-    tz, ty, cx, cg, us = op.autotune(binding.SPARC_F32, 5)
+    tz, ty, cx, cg, cb, us = op.autotune(binding.SPARC_F32, 5)
     assert us > 0 and (tz, ty) in [(32, 16), (32, 32), (32, 64)] and 1 <= cx <= 30 and 1 <= cg <= 5
-    assert op.step_config(binding.SPARC_F32, 5) == (tz, ty, cx, cg)
+    assert cb in (1, 2)
+    assert op.step_config(binding.SPARC_F32, 5) == (tz, ty, cx, cg, cb)
     tuned = op.cheb_filter(Xd, 9, *bounds)
     oref = oracle.cheb_filter(inputs.round_cluster_f32(cl), X, 9, *bounds)
     for ty in (16, 32, 64):
         base = None
-        for ch, cg in ((0, 0), (8, 1), (16, 3), (30, 8)):
-            op.set_launch(binding.SPARC_F32, 32, ty, ch, cg)
+        for ch, cg, cb in ((0, 0, 1), (8, 1, 2), (16, 3, 1), (30, 8, 2), (0, 2, 2)):
+            op.set_launch(binding.SPARC_F32, 32, ty, ch, cg, cb)
             assert op.step_config(binding.SPARC_F32, 5)[:2] == (32, ty)
+            assert op.step_config(binding.SPARC_F32, 5)[4] == cb
             got = op.cheb_filter(Xd, 9, *bounds)
             if base is None:
                 base = got
-            assert torch.equal(got, base), (ty, ch, cg)
+            assert torch.equal(got, base), (ty, ch, cg, cb)
             g = got.double().cpu().numpy()
             err = (np.linalg.norm(g - oref, axis=1) / np.linalg.norm(oref, axis=1)).max()
             assert err <= 5e-5, (ty, ch, cg, err)
@@ -118,3 +122,5 @@ def test_autotune_and_launch_choices():
             assert torch.equal(tuned, ref)
     with pytest.raises(binding.SparcError):
         op.set_launch(binding.SPARC_F32, 32, 8, 0)  # 8-row patches are FP64 only
+    with pytest.raises(binding.SparcError):
+        op.set_launch(binding.SPARC_F32, 32, 32, 0, 0, 3)  # one or two columns per workgroup

@@ -462,15 +462,16 @@ def test_vector_step_edges(case, dtype):
     href = oracle.h_apply(ocl, X)
     fref = oracle.cheb_filter(ocl, X, m, a0, a, b)
     for ty in heights:
-        op.set_launch(code, 32, ty, 0)
-        assert op.step_config(code, ns)[:2] == (32, ty)
-        outbig = torch.full((ns, cl.nd + 2 * pad), 7.0, dtype=tdt, device="cuda")
-        op.h_apply(Xv, outbig[:, : cl.nd])
-        assert rel_err(host(outbig[:, : cl.nd]), href) <= tol, ty
-        assert torch.all(outbig[:, cl.nd:] == 7.0)  # padding untouched
-        e = rel_err(host(op.cheb_filter(Xv, m, a0, a, b)), fref)
-        print(f"{n} {dtype} TY={ty} filter err {e:.2e}")
-        assert e <= tol, ty
+        for cb in (1, 2):
+            op.set_launch(code, 32, ty, 0, 0, cb)
+            assert op.step_config(code, ns)[:2] == (32, ty) and op.step_config(code, ns)[4] == cb
+            outbig = torch.full((ns, cl.nd + 2 * pad), 7.0, dtype=tdt, device="cuda")
+            op.h_apply(Xv, outbig[:, : cl.nd])
+            assert rel_err(host(outbig[:, : cl.nd]), href) <= tol, (ty, cb)
+            assert torch.all(outbig[:, cl.nd:] == 7.0)  # padding untouched
+            e = rel_err(host(op.cheb_filter(Xv, m, a0, a, b)), fref)
+            print(f"{n} {dtype} TY={ty} col_block {cb} filter err {e:.2e}")
+            assert e <= tol, (ty, cb)
 
 
 def test_crowded_patches_fall_back():
