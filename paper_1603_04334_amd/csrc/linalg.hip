@@ -14,8 +14,9 @@
 // formed in FP64 by the fused kernels (an FP32 block is widened as it is
 // loaded), H_s = Y^T (H Y) and M_s = Y^T Y come from one FP64 matrix-core
 // kernel, and the symmetric-definite problem is solved on the device: in one
-// workgroup (Cholesky + Jacobi) for up to 64 columns, by rocSOLVER's dsygvd
-// beyond.
+// workgroup (Cholesky + Jacobi) for up to 64 columns, beyond by rocSOLVER's
+// Cholesky and divide-and-conquer eigensolver with the reduction to standard
+// form and the back-transformation as rocBLAS triangular solves.
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -366,7 +367,10 @@ __global__ void f64_to_f32_dense(const double *src, float *dst, long long n)
 // column panels in LDS (coalesced along the contiguous grid axis) and writes
 // its partial tiles, which a second kernel sums in chunk order; the upper
 // triangle is then mirrored.  Each of the four waves owns a 32 x 32 quarter of
-// both tiles (2 x 2 MFMA blocks each).
+// both tiles (2 x 2 MFMA blocks each).  Workgroup indices are remapped so
+// that all tile pairs of one chunk run back to back on the same XCD: the ten
+// pairs that read a column panel then share it in that XCD's L2, and each
+// panel of a chunk comes from HBM about once.
 
 constexpr int kRrTile = 64;
 constexpr int kRrK = 32;
@@ -390,16 +394,21 @@ __global__ void __launch_bounds__(256) rr_project_kernel(const TY *__restrict__ 
     __shared__ double sA[kRrTile][kRrK + 1];  // Y columns of the row tile, [col][k]
     __shared__ double sB[kRrTile][kRrK + 1];  // Y columns of the column tile
     __shared__ double sH[kRrTile][kRrK + 1];  // HY columns of the column tile
-    // tile pair (ti <= tj) number blockIdx.y, pairs in row order: both
-    // matrices are symmetric, so only the upper tiles are formed
+    // (chunk, tile pair) from the XCD-contiguous workgroup order; tile pair
+    // (ti <= tj) numbered in row order: both matrices are symmetric, so only
+    // the upper tiles are formed
     const int nt = (ns + kRrTile - 1) / kRrTile;
-    int ti = 0, rem = blockIdx.y;
+    const int npairs = nt * (nt + 1) / 2;
+    const int nb = (int)gridDim.x, wg = (int)blockIdx.x, xcd = wg & 7;
+    const int t = xcd * (nb >> 3) + min(xcd, nb & 7) + (wg >> 3);
+    const int chunk = t / npairs;
+    int ti = 0, rem = t % npairs;
     while (rem >= nt - ti) {
         rem -= nt - ti;
         ++ti;
     }
     const int tj = ti + rem;
-    const long long k0 = blockIdx.x * kchunk;
+    const long long k0 = chunk * kchunk;
     const long long k1 = (k0 + kchunk < nd) ? k0 + kchunk : nd;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -459,7 +468,7 @@ __global__ void __launch_bounds__(256) rr_project_kernel(const TY *__restrict__ 
     }
     // partial[(chunk*2 + which)][col][row] of the full ns x ns matrices
     const long long mat = (long long)ns * ns;
-    double *pm = partial + (long long)blockIdx.x * 2 * mat;
+    double *pm = partial + (long long)chunk * 2 * mat;
     double *ph = pm + mat;
 #pragma unroll
     for (int u = 0; u < 2; ++u)
@@ -654,7 +663,8 @@ struct BlasLease {
 };
 // A HIP error state left behind by a library call that itself reported
 // success.  The one code seen so far (hipErrorStreamCaptureUnsupported, after
-// rocsolver_dsygvd on worker threads that capture nothing) is cleared and
+// rocSOLVER's generalized eigensolver on worker threads that capture nothing)
+// is cleared and
 // counted, with its first occurrences written to stderr; any other code fails
 // the call.
 std::atomic<long long> g_cleared_errors{0};
@@ -828,11 +838,12 @@ int sparc_lanczos(const sparc_op *op, int32_t k, const double *v0, double *alpha
 
 static long long rr_chunk(long long nd, int ns)
 {
-    // about 512 workgroups in total (upper tile pairs x chunks), chunks a
-    // multiple of the staged slice
+    // at least 512 workgroups in total (upper tile pairs x chunks) and at
+    // least 8 chunks per XCD; chunks a multiple of the staged slice
     const long long nt = (ns + kRrTile - 1) / kRrTile;
     const long long tiles = nt * (nt + 1) / 2;
-    long long nch = std::max<long long>(1, 512 / tiles);
+    long long nch = std::max<long long>(64, (512 + tiles - 1) / tiles);
+    nch = std::max<long long>(1, std::min<long long>(nch, nd / kRrK));
     long long c = (nd + nch - 1) / nch;
     c = (c + kRrK - 1) / kRrK * kRrK;
     return std::max<long long>(c, kRrK);
@@ -885,7 +896,7 @@ int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_
     const long long kc = rr_chunk(nd, ns);
     const int nch = (int)((nd + kc - 1) / kc);
     const int nt = (ns + kRrTile - 1) / kRrTile;
-    const dim3 pg(nch, nt * (nt + 1) / 2, 1);
+    const dim3 pg((unsigned)(nch * (nt * (nt + 1) / 2)), 1, 1);
     if (dtype == SPARC_F64) {
         const FLaunch V = choose_vec_launch(op, SPARC_F64, ns, {ldy, nd});
         if ((st = launch_h_step(op, SPARC_F64, Y, ldy, nullptr, 0, HY, nd, ns, G, hc, L, s, &V))) return st;
@@ -918,13 +929,45 @@ int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_
         const hipError_t before = hipGetLastError();
         if (before != hipSuccess)
             return fail(SPARC_E_HIP, std::string("HIP error pending before the eigensolver: ") + hipGetErrorString(before));
-        const rocblas_status rs = rocsolver_dsygvd(hb, rocblas_eform_ax, evec ? rocblas_evect_original : rocblas_evect_none,
-                                                   rocblas_fill_upper, ns, Hs, ns, Ms, ns, D, E, info);
-        const hipError_t after = hipGetLastError();
-        if (rs != rocblas_status_success)
-            return fail(SPARC_E_HIP, std::string("rocsolver_dsygvd failed: ") + rocblas_status_to_string(rs) +
-                                         (after != hipSuccess ? std::string(", HIP: ") + hipGetErrorString(after) : ""));
-        if (after != hipSuccess && (st = note_library_error("rocsolver_dsygvd", after))) return st;
+        // M_s = U^T U (rocSOLVER Cholesky); the reduction to the standard
+        // problem C = U^-T H_s U^-1 and the back-transformation q = U^-1 z by
+        // blocked triangular solves (rocBLAS trsm); C z = theta z by rocSOLVER's
+        // divide-and-conquer symmetric eigensolver.  (rocsolver_dsygvd's own
+        // reduction issues ~600 matrix-vector solves per call at N_s = 600.)
+        auto lib_call = [&](const char *what, rocblas_status rs) -> int {
+            const hipError_t after = hipGetLastError();
+            if (rs != rocblas_status_success)
+                return fail(SPARC_E_HIP, std::string(what) + " failed: " + rocblas_status_to_string(rs) +
+                                             (after != hipSuccess ? std::string(", HIP: ") + hipGetErrorString(after) : ""));
+            if (after != hipSuccess) return note_library_error(what, after);
+            return SPARC_OK;
+        };
+        if ((st = lib_call("rocsolver_dpotrf", rocsolver_dpotrf(hb, rocblas_fill_upper, ns, Ms, ns, info)))) return st;
+        int pinfo = 0;
+        SPARC_HIP(hipMemcpyAsync(&pinfo, info, sizeof(int), hipMemcpyDeviceToHost, s));
+        SPARC_HIP(hipStreamSynchronize(s));
+        if (pinfo != 0) {
+            g_rr_rank_deficient = true;
+            return fail(SPARC_E_BREAKDOWN, "Cholesky of M_s failed (info=" + std::to_string(pinfo) +
+                                               "): the filtered block is numerically rank deficient");
+        }
+        const double one = 1.0;
+        if ((st = lib_call("rocblas_dtrsm", rocblas_dtrsm(hb, rocblas_side_left, rocblas_fill_upper,
+                                                          rocblas_operation_transpose, rocblas_diagonal_non_unit, ns,
+                                                          ns, &one, Ms, ns, Hs, ns))))
+            return st;
+        if ((st = lib_call("rocblas_dtrsm", rocblas_dtrsm(hb, rocblas_side_right, rocblas_fill_upper,
+                                                          rocblas_operation_none, rocblas_diagonal_non_unit, ns, ns,
+                                                          &one, Ms, ns, Hs, ns))))
+            return st;
+        if ((st = lib_call("rocsolver_dsyevd",
+                           rocsolver_dsyevd(hb, evec ? rocblas_evect_original : rocblas_evect_none, rocblas_fill_upper,
+                                            ns, Hs, ns, D, E, info))))
+            return st;
+        if (evec && (st = lib_call("rocblas_dtrsm", rocblas_dtrsm(hb, rocblas_side_left, rocblas_fill_upper,
+                                                                 rocblas_operation_none, rocblas_diagonal_non_unit, ns,
+                                                                 ns, &one, Ms, ns, Hs, ns))))
+            return st;
     }
     int hinfo = 0;
     SPARC_HIP(hipMemcpyAsync(theta, D, ns * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -934,11 +977,11 @@ int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_
     if (hinfo != 0) {
         if (ns <= 64 && hinfo == ns + 1)
             return fail(SPARC_E_BREAKDOWN, "Jacobi eigensolver did not converge within its sweep limit");
-        if (ns > 64 && hinfo <= ns)
-            return fail(SPARC_E_BREAKDOWN, "rocsolver_dsygvd: the tridiagonal eigensolver did not converge (info=" +
+        if (ns > 64)
+            return fail(SPARC_E_BREAKDOWN, "rocsolver_dsyevd: the tridiagonal eigensolver did not converge (info=" +
                                                std::to_string(hinfo) + ")");
-        // the Cholesky factorisation of M_s failed (small solver: info = the
-        // failing column; rocSOLVER: info = ns + that column)
+        // the small solver's Cholesky factorisation of M_s failed (info = the
+        // failing column)
         g_rr_rank_deficient = true;
         return fail(SPARC_E_BREAKDOWN, "Cholesky of M_s failed (info=" + std::to_string(hinfo) +
                                            "): the filtered block is numerically rank deficient");
