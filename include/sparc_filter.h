@@ -520,7 +520,8 @@ int sparc_stream_copy(void *dst, const void *src, size_t bytes, void *stream);
 const char *sparc_status_str(int status);
 const char *sparc_last_error(void);
 
-/* Number of times a library call (rocsolver_dsygvd) returned success but left
+/* Number of times a rocSOLVER / rocBLAS call of the Rayleigh-Ritz eigensolver
+ * returned success but left
  * the thread's HIP error state set to hipErrorStreamCaptureUnsupported, which
  * the library then cleared (each occurrence up to the eighth is also written
  * to stderr).  Any other error code left behind fails the call with
@@ -542,7 +543,8 @@ int sparc_profile_reset(void);
 /* Override the launch configuration of the vector step kernels (the fused
  * stencil / potential / projector scatter / recurrence pass with the
  * projections of its result) for one dtype: patch extent along z and y
- * (tile_z = 32; tile_y 16, 32 or 64 for FP32, 8, 16 or 32 for FP64), the
+ * (tile_z = 32 with tile_y 16, 32 or 64 for FP32, 8, 16 or 32 for FP64;
+ * tile_z = 64 with tile_y 16 or 32 for FP32, 8 or 16 for FP64), the
  * number of x-planes per workgroup (chunk_x <= 0: library choice; rounded up
  * to a multiple of 8) and the column group (col_group <= 0: library choice;
  * that many column blocks of one patch go to consecutive workgroups, so they
@@ -576,7 +578,7 @@ int sparc_autotune(sparc_op *op, int32_t dtype, int32_t ns, void *stream, int32_
 
 /* Launch configuration of the step kernels for a dtype and ns as chosen by
  * the library for the op (out parameters may be NULL).  For grids the vector
- * kernels take: tile_z = 32, tile_y, chunk_x, col_group and col_block of the
+ * kernels take: tile_z, tile_y, chunk_x, col_group and col_block of the
  * vector launch; otherwise the scalar kernels' patch (32 x 16), x-chunk and
  * col_group = col_block = 1. */
 int sparc_step_config(const sparc_op *op, int32_t dtype, int32_t ns, int32_t *tile_z, int32_t *tile_y,

@@ -414,10 +414,10 @@ int sparc_op_set_launch(sparc_op *op, int32_t dtype, int32_t tile_z, int32_t til
     if (tile_z <= 0 && tile_y <= 0) {
         op->tune_shape[dtype] = -1;
     } else {
-        // patches of TY x 32 nodes: TY in 16, 32, 64 (FP32) or 8, 16, 32 (FP64)
+        // patches of TY x TZ nodes offered for the dtype
         int found = -1;
         for (int p = 0; p < kNumPlans; ++p)
-            if (tile_z == 32 && kPlanTY[p] == tile_y && vec_plan_valid(dtype, p)) found = p;
+            if (kPlanTZ[p] == tile_z && kPlanTY[p] == tile_y && vec_plan_valid(dtype, p)) found = p;
         if (found < 0) return fail(SPARC_E_ARG, "unsupported tile shape");
         op->tune_shape[dtype] = found;
     }
@@ -434,7 +434,7 @@ int sparc_step_config(const sparc_op *op, int32_t dtype, int32_t ns, int32_t *ti
     if (!op || ns < 1 || (dtype != SPARC_F64 && dtype != SPARC_F32)) return fail(SPARC_E_ARG, "null op, ns < 1 or bad dtype");
     const FLaunch V = choose_vec_launch(op, dtype, ns, {});
     if (V.plan >= 0) {
-        if (tile_z) *tile_z = 32;
+        if (tile_z) *tile_z = kPlanTZ[V.plan];
         if (tile_y) *tile_y = kPlanTY[V.plan];
         if (chunk_x) *chunk_x = V.chunk_x;
         if (col_group) *col_group = std::min(V.cgroup, (ns + V.cblk - 1) / V.cblk);

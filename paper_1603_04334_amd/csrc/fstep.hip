@@ -9,8 +9,9 @@
 // alpha V_nl yk (Sec. 3.1 Eq. non-localPS:FD).
 //
 // Data movement (HBM-bound):
-//  * A workgroup owns a TY x 32 patch of the (y, z) plane of one column and
-//    streams it along x.  Each lane owns one unit of consecutive z nodes of one
+//  * A workgroup owns a TY x TZ patch (TZ = 32 or 64 nodes) of the (y, z)
+//    plane of one column and streams it along x (64-wide patches halve the
+//    share of the z halo, whose two partial lines per row are fetched whole).  Each lane owns one unit of consecutive z nodes of one
 //    y row: 4 FP32 or 2 FP64 values, 16 bytes, so every global access is a
 //    16-byte raw buffer load or store (a plain copy with 4-byte accesses per
 //    lane reaches about 60% of the bandwidth of 16-byte accesses on this
@@ -43,20 +44,26 @@ namespace sparc {
 
 static int vec_width(int dtype) { return dtype == SPARC_F64 ? 2 : 4; }
 
-// patch heights offered per dtype: TY 8, 16, 32 (FP64) and 16, 32, 64 (FP32)
-static int vec_plan_lo(int dtype) { return dtype == SPARC_F64 ? 0 : 1; }
+// patches offered per dtype (TY x TZ): FP64 8, 16, 32 x 32 and 8, 16 x 64;
+// FP32 16, 32, 64 x 32 and 16, 32 x 64 (128 to 512 threads)
 static int vec_default_plan(int dtype) { return dtype == SPARC_F64 ? 1 : 2; }  // 16 x 32 FP64, 32 x 32 FP32
 
-static int vec_nt(int dtype, int plan) { return (kFTZ / vec_width(dtype)) * kPlanTY[plan]; }
+static int vec_nt(int dtype, int plan) { return (kPlanTZ[plan] / vec_width(dtype)) * kPlanTY[plan]; }
 
-bool vec_plan_valid(int dtype, int plan) { return plan >= vec_plan_lo(dtype) && plan < vec_plan_lo(dtype) + 3; }
+bool vec_plan_valid(int dtype, int plan)
+{
+    static const bool f64[kNumPlans] = {true, true, true, false, true, true, false};
+    static const bool f32[kNumPlans] = {false, true, true, true, false, true, true};
+    if (plan < 0 || plan >= kNumPlans) return false;
+    return dtype == SPARC_F64 ? f64[plan] : f32[plan];
+}
 
 // split x so that about 8192 waves are in flight (at most kMaxChunks chunks,
 // at least 4 planes each)
 static int vec_default_chunks(const sparc_op *op, int dtype, int plan, int ns)
 {
-    const int ty = kPlanTY[plan];
-    const long long tiles = (long long)((op->n[1] + ty - 1) / ty) * ((op->n[2] + kFTZ - 1) / kFTZ);
+    const int ty = kPlanTY[plan], tz = kPlanTZ[plan];
+    const long long tiles = (long long)((op->n[1] + ty - 1) / ty) * ((op->n[2] + tz - 1) / tz);
     const long long waves = tiles * ns * (vec_nt(dtype, plan) / 64);
     long long nch = (8192 + waves - 1) / waves;
     nch = std::max<long long>(1, std::min<long long>({nch, (long long)kMaxChunks, (long long)op->n[0] / 4}));
@@ -103,8 +110,8 @@ static int launch_fstep_t(const sparc_op *op, const FLaunch &L, const void *yk, 
                           int64_t ldp, void *out, int64_t ldo, int ns, void *part, const StepCoef &c,
                           hipStream_t stream)
 {
-    const int ty = kPlanTY[L.plan];
-    const int nt = (kFTZ / VecTraits<T>::N) * ty;
+    const int ty = kPlanTY[L.plan], tz = kPlanTZ[L.plan];
+    const int nt = (tz / VecTraits<T>::N) * ty;
     FStepArgs<T> a;
     std::memset(&a, 0, sizeof(a));
     a.yk = (const T *)yk;
@@ -118,7 +125,7 @@ static int launch_fstep_t(const sparc_op *op, const FLaunch &L, const void *yk, 
     a.n2 = op->n[1];
     a.n3 = op->n[2];
     a.tiles_y = (op->n[1] + ty - 1) / ty;
-    a.tiles_z = (op->n[2] + kFTZ - 1) / kFTZ;
+    a.tiles_z = (op->n[2] + tz - 1) / tz;
     a.chunk_x = L.chunk_x;
     a.nchunks = L.nchunks;
     const int cb = L.cblk == 2 ? 2 : 1;
@@ -168,16 +175,30 @@ static int launch_fstep_t(const sparc_op *op, const FLaunch &L, const void *yk, 
     ProfScope prof(prev ? 0 : 3, stream);
     const int natoms = std::max(op->natoms, 1);
     if constexpr (std::is_same<T, float>::value) {
-        switch (ty) {
-            case 16: return fstep_f32_ty16(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
-            case 32: return fstep_f32_ty32(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
-            case 64: return fstep_f32_ty64(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
+        if (tz == 64) {
+            switch (ty) {
+                case 16: return fstep_f32_ty16_tz64(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
+                case 32: return fstep_f32_ty32_tz64(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
+            }
+        } else {
+            switch (ty) {
+                case 16: return fstep_f32_ty16(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
+                case 32: return fstep_f32_ty32(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
+                case 64: return fstep_f32_ty64(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
+            }
         }
     } else {
-        switch (ty) {
-            case 8: return fstep_f64_ty8(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
-            case 16: return fstep_f64_ty16(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
-            case 32: return fstep_f64_ty32(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
+        if (tz == 64) {
+            switch (ty) {
+                case 8: return fstep_f64_ty8_tz64(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
+                case 16: return fstep_f64_ty16_tz64(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
+            }
+        } else {
+            switch (ty) {
+                case 8: return fstep_f64_ty8(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
+                case 16: return fstep_f64_ty16(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
+                case 32: return fstep_f64_ty32(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
+            }
         }
     }
     return fail(SPARC_E_ARG, "patch height not available for this dtype");

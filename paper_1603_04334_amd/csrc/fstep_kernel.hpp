@@ -8,7 +8,7 @@
 
 namespace sparc {
 
-constexpr int kFTZ = 32;  // patch extent along z (grid points)
+constexpr int kFTZ = 32;  // default patch extent along z (grid points)
 
 template <typename T>
 struct VecTraits;
@@ -56,12 +56,11 @@ struct FStepArgs {
 
 // B: columns per workgroup.  With B = 2 the two columns of one patch share
 // the V_eff loads, the halo offsets and the plane loop (orbital blocking).
-template <typename T, int TY, bool PREV, bool STREAM, int B = 1>
+template <typename T, int TY, bool PREV, bool STREAM, int B = 1, int TZ = kFTZ>
 struct FStep {
     static constexpr int R = kMaxRadius;
     static constexpr int VZ = VecTraits<T>::N;
     using V = typename VecTraits<T>::V;
-    static constexpr int TZ = kFTZ;
     static constexpr int LPR = TZ / VZ;  // lanes per row of the patch
     static constexpr int NT = LPR * TY;
     static constexpr int NW = NT / 64;

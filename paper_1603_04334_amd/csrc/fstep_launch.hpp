@@ -12,11 +12,11 @@ namespace sparc {
 // ngb run NT/256 projector-gather items of yk each (item = atom + natoms *
 // (column block + ncb * split), 256 threads apiece; a group past the last
 // item only joins the item's barrier), filling CUs as the step drains.
-template <typename T, int TY, bool PREV, bool STREAM, bool TAIL, int B>
-__global__ void __launch_bounds__((kFTZ / VecTraits<T>::N) * TY)
+template <typename T, int TY, int TZ, bool PREV, bool STREAM, bool TAIL, int B>
+__global__ void __launch_bounds__((TZ / VecTraits<T>::N) * TY)
     fstep_kernel(const FStepArgs<T> a, const GatherArgs<T, T> g, int natoms, int ncb, int nitems)
 {
-    constexpr int NT = (kFTZ / VecTraits<T>::N) * TY;
+    constexpr int NT = (TZ / VecTraits<T>::N) * TY;
     if constexpr (TAIL) {
         if ((int)blockIdx.x >= a.nblocks) {
             constexpr int G = NT / 256;
@@ -31,20 +31,20 @@ __global__ void __launch_bounds__((kFTZ / VecTraits<T>::N) * TY)
             return;
         }
     }
-    using K = FStep<T, TY, PREV, STREAM, B>;
+    using K = FStep<T, TY, PREV, STREAM, B, TZ>;
     __shared__ __align__(16) typename K::Shared sh;
     K k(a);
     k.run(blockIdx.x, sh);
 }
 
-template <typename T, int TY, int B>
+template <typename T, int TY, int TZ, int B>
 int fstep_dispatch_b(const FStepArgs<T> &a, const GatherArgs<T, T> &g, int natoms, int ncb, int nitems, int ngb,
                      bool prev, bool strm, hipStream_t s)
 {
-    constexpr int NT = (kFTZ / VecTraits<T>::N) * TY;
+    constexpr int NT = (TZ / VecTraits<T>::N) * TY;
     const dim3 grid(a.nblocks + ngb), b(NT);
 #define SPARC_FS(P, S, G) \
-    hipLaunchKernelGGL((fstep_kernel<T, TY, P, S, G, B>), grid, b, 0, s, a, g, natoms, ncb, nitems)
+    hipLaunchKernelGGL((fstep_kernel<T, TY, TZ, P, S, G, B>), grid, b, 0, s, a, g, natoms, ncb, nitems)
     // patches of fewer than 256 threads cannot host a gather item
     if (ngb > 0 && NT < 256) return fail(SPARC_E_ARG, "gather tail needs 256-thread workgroups");
     if constexpr (NT < 256) {
@@ -81,12 +81,12 @@ int fstep_dispatch_b(const FStepArgs<T> &a, const GatherArgs<T, T> &g, int natom
 }
 
 // cblk: columns per workgroup (1 or 2)
-template <typename T, int TY>
+template <typename T, int TY, int TZ = kFTZ>
 int fstep_dispatch(const FStepArgs<T> &a, const GatherArgs<T, T> &g, int natoms, int ncb, int nitems, int ngb,
                    bool prev, bool strm, int cblk, hipStream_t s)
 {
-    if (cblk == 2) return fstep_dispatch_b<T, TY, 2>(a, g, natoms, ncb, nitems, ngb, prev, strm, s);
-    return fstep_dispatch_b<T, TY, 1>(a, g, natoms, ncb, nitems, ngb, prev, strm, s);
+    if (cblk == 2) return fstep_dispatch_b<T, TY, TZ, 2>(a, g, natoms, ncb, nitems, ngb, prev, strm, s);
+    return fstep_dispatch_b<T, TY, TZ, 1>(a, g, natoms, ncb, nitems, ngb, prev, strm, s);
 }
 
 // per (type, patch height) launches, one translation unit each
@@ -98,6 +98,10 @@ SPARC_FSTEP_DECL(fstep_f32_ty64, float)
 SPARC_FSTEP_DECL(fstep_f64_ty8, double)
 SPARC_FSTEP_DECL(fstep_f64_ty16, double)
 SPARC_FSTEP_DECL(fstep_f64_ty32, double)
+SPARC_FSTEP_DECL(fstep_f32_ty16_tz64, float)
+SPARC_FSTEP_DECL(fstep_f32_ty32_tz64, float)
+SPARC_FSTEP_DECL(fstep_f64_ty8_tz64, double)
+SPARC_FSTEP_DECL(fstep_f64_ty16_tz64, double)
 #undef SPARC_FSTEP_DECL
 
 }  // namespace sparc

@@ -30,9 +30,10 @@ struct AtomDev {
     long long chi0;   // offset of the atom's chi block (nproj * nbox values)
 };
 
-// Patch heights of the vector step kernels (patches of TY x 32 nodes in y, z)
-constexpr int kNumPlans = 4;
-constexpr int kPlanTY[kNumPlans] = {8, 16, 32, 64};
+// Patches of the vector step kernels: TY x TZ nodes in (y, z) per plan
+constexpr int kNumPlans = 7;
+constexpr int kPlanTY[kNumPlans] = {8, 16, 32, 64, 8, 16, 32};
+constexpr int kPlanTZ[kNumPlans] = {32, 32, 32, 32, 64, 64, 64};
 
 // Tile shapes of the fused step kernel: a workgroup of nt threads owns a
 // TY x TZ patch of the (y, z) plane and streams it along x.  TZ lanes run

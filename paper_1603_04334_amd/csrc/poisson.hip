@@ -16,10 +16,11 @@
 //    its square;
 //  * CG iteration: q = A p through the fused stencil kernel of H on a
 //    zero-potential operator (A = (1/2 pi) (-1/2 lap_h)), then p.q, then one
-//    kernel per block-Jacobi group that updates x and r, multiplies each block
-//    of r by the inverse of A restricted to the block (a dense symmetric
-//    matrix, one per block shape, kept in L2) and forms the partials of r.z
-//    and r.r, then the update of p.  Scalars never leave the device: every
+//    kernel that updates x and r, multiplies each block of r by the inverse of
+//    A restricted to the block (a dense symmetric matrix, one per block shape,
+//    kept in L2; blocks are taken in bricks along z so that global accesses
+//    are coalesced rows) and forms the partials of r.z and r.r, then the
+//    update of p.  Scalars never leave the device: every
 //    workgroup finishes the partial sums it needs in the same fixed order, so
 //    alpha, beta and the convergence test are bitwise the same everywhere.
 //    The host enqueues iterations in chunks and reads one flag per chunk;
@@ -290,7 +291,13 @@ __device__ __forceinline__ int bj_shape(const BjGeo &q, int bi, int bj, int bk, 
     return code;
 }
 
-// block-Jacobi step over all blocks, `groups` blocks at a time per workgroup:
+// block-Jacobi step over all blocks.  A workgroup takes a brick of G = 256 /
+// (b0 b1 b2) blocks that follow each other along z in one (block x, block y)
+// row, so its global accesses are rows of G b2 consecutive nodes (coalesced):
+// thread t owns node (a, b, zz) of the brick, t = (a b1 + b) G b2 + zz.  The
+// residual goes through LDS into block order, thread (slot, row) forms row
+// `row` of M^-1 r for block `slot` (sum over j ascending), and the result goes
+// back through LDS to the brick order for the coalesced store.
 // UPDATE: alpha = rz_old / pq, x += alpha p, r -= alpha q; both modes:
 // z = M^-1 r per block, p = z (INIT only), partials of r.z and r.r
 template <bool UPDATE>
@@ -302,28 +309,35 @@ __global__ void __launch_bounds__(kPT)
 {
     __shared__ double red[4];
     __shared__ double rs[kPT];
+    __shared__ double zs[kPT];
     if (UPDATE && state->done) return;
     double alpha = 0.0;
     if (UPDATE) alpha = sum_partials(part_rz_old, n_rz_old, red) / sum_partials(part_pq, n_pq, red);
-    const int G = kPT / q.maxm;  // blocks in flight per workgroup
-    const int slot = threadIdx.x / q.maxm, row = threadIdx.x % q.maxm;
+    const int G = kPT / q.maxm;          // blocks per brick
+    const int bpr = (q.nb[2] + G - 1) / G;  // bricks per (block x, block y) row
+    const long long nbricks = (long long)q.nb[0] * q.nb[1] * bpr;
+    // brick-order coordinates of this thread
+    const int zw = G * q.b[2];
+    const int ta = threadIdx.x / (q.b[1] * zw), tb = (threadIdx.x / zw) % q.b[1], tz = threadIdx.x % zw;
+    const bool tin = threadIdx.x < q.b[0] * q.b[1] * zw;
+    const int tslot = tz / q.b[2], tzl = tz % q.b[2];
+    // block-order coordinates of this thread (compute phase)
+    const int cslot = threadIdx.x / q.maxm, crow = threadIdx.x % q.maxm;
     double arz = 0.0, arr = 0.0;
-    for (long long b0 = (long long)blockIdx.x * G; b0 < q.nblocks; b0 += (long long)gridDim.x * G) {
-        const long long b = b0 + slot;
-        bool act = slot < G && b < q.nblocks;
-        int dim[3] = {1, 1, 1}, code = 0;
+    for (long long br = blockIdx.x; br < nbricks; br += gridDim.x) {
+        const int bk0 = (int)(br % bpr) * G;
+        const long long u = br / bpr;
+        const int bj = (int)(u % q.nb[1]), bi = (int)(u / q.nb[1]);
+        // load phase: this thread's node of the brick
+        int dim[3] = {1, 1, 1};
+        bool act = tin && bk0 + tslot < q.nb[2];
         long long node = 0;
+        int lrow = 0;
         if (act) {
-            const int bk = (int)(b % q.nb[2]);
-            const long long u = b / q.nb[2];
-            const int bj = (int)(u % q.nb[1]), bi = (int)(u / q.nb[1]);
-            code = bj_shape(q, bi, bj, bk, dim);
-            const int m = dim[0] * dim[1] * dim[2];
-            act = row < m;
-            if (act) {
-                const int a0 = row / (dim[1] * dim[2]), a1 = (row / dim[2]) % dim[1], a2 = row % dim[2];
-                node = ((long long)(bi * q.b[0] + a0) * q.n1 + (bj * q.b[1] + a1)) * q.n2 + (bk * q.b[2] + a2);
-            }
+            (void)bj_shape(q, bi, bj, bk0 + tslot, dim);
+            act = ta < dim[0] && tb < dim[1] && tzl < dim[2];
+            lrow = (ta * dim[1] + tb) * dim[2] + tzl;
+            node = ((long long)(bi * q.b[0] + ta) * q.n1 + (bj * q.b[1] + tb)) * q.n2 + ((bk0 + tslot) * q.b[2] + tzl);
         }
         double rv = 0.0;
         if (act) {
@@ -334,15 +348,26 @@ __global__ void __launch_bounds__(kPT)
             } else {
                 rv = r[node];
             }
+            rs[tslot * q.maxm + lrow] = rv;
         }
-        rs[threadIdx.x] = rv;
         __syncthreads();
+        // compute phase: row crow of block cslot
+        if (cslot < G && bk0 + cslot < q.nb[2]) {
+            int cd[3];
+            const int code = bj_shape(q, bi, bj, bk0 + cslot, cd);
+            const int m = cd[0] * cd[1] * cd[2];
+            if (crow < m) {
+                const double *M = minv + (long long)code * q.maxm * q.maxm;
+                const double *rb = rs + cslot * q.maxm;
+                double zv = 0.0;
+                for (int j = 0; j < m; ++j) zv += M[(long long)j * m + crow] * rb[j];
+                zs[cslot * q.maxm + crow] = zv;
+            }
+        }
+        __syncthreads();
+        // store phase, brick order again
         if (act) {
-            const int m = dim[0] * dim[1] * dim[2];
-            const double *M = minv + (long long)code * q.maxm * q.maxm;
-            const double *rb = rs + slot * q.maxm;
-            double zv = 0.0;
-            for (int j = 0; j < m; ++j) zv += M[(long long)j * m + row] * rb[j];
+            const double zv = zs[tslot * q.maxm + lrow];
             z[node] = zv;
             if (!UPDATE) p[node] = zv;
             arz += rv * zv;
@@ -622,7 +647,8 @@ extern "C" int sparc_poisson_create(const sparc_grid *grid, int32_t lmax, const 
     P->nmom = (int)std::max<long long>(1, std::min<long long>(256, (nd + kPT - 1) / kPT));
     P->nred = (int)std::max<long long>(1, std::min<long long>(kRedMax, (nd + 4 * kPT - 1) / (4 * kPT)));
     const int G = kPT / q.maxm;
-    P->nbjg = (int)std::max<long long>(1, std::min<long long>(kRedMax, (q.nblocks + G - 1) / G));
+    const long long bricks = (long long)q.nb[0] * q.nb[1] * ((q.nb[2] + G - 1) / G);
+    P->nbjg = (int)std::max<long long>(1, std::min<long long>(kRedMax, bricks));
     *out = P;
     return SPARC_OK;
 }

@@ -102,7 +102,6 @@ extern "C" int sparc_autotune(sparc_op *op, int32_t dtype, int32_t ns, void *str
         const int saved_shape = op->tune_shape[dtype], saved_chunk = op->tune_chunk[dtype];
         const int saved_ns = op->tune_ns[dtype], saved_group = op->tune_group[dtype];
         const int saved_cblk = op->tune_cblk[dtype];
-        const int lo = dtype == SPARC_F64 ? 0 : 1;
         const int n1 = op->n[0];
         const int chunks[] = {0, n1, (n1 + 1) / 2, (n1 + 3) / 4, (n1 + 7) / 8};
         const size_t pb = std::max<size_t>(gather_bytes(op, dtype, ns), 256);
@@ -126,7 +125,8 @@ extern "C" int sparc_autotune(sparc_op *op, int32_t dtype, int32_t ns, void *str
         const StepLaunch Ls = choose_step_launch(op, dtype, ns);
         int st = SPARC_OK;
         const int groups[] = {1, 4, 8, 16};
-        for (int p = lo; p < lo + 3 && st == SPARC_OK; ++p) {
+        for (int p = 0; p < kNumPlans && st == SPARC_OK; ++p) {
+            if (!vec_plan_valid(dtype, p)) continue;
             for (int ci = 0; ci < 5 && st == SPARC_OK; ++ci) {
                 if (chunks[ci] > 0 && chunks[ci] < 4) continue;
                 for (int cb = 1; cb <= 2 && st == SPARC_OK; ++cb) {
@@ -178,7 +178,7 @@ extern "C" int sparc_autotune(sparc_op *op, int32_t dtype, int32_t ns, void *str
     op->tune_group[dtype] = best.group;
     op->tune_cblk[dtype] = best.cblk;
     op->tune_ns[dtype] = ns;  // the choice holds for this block width only
-    if (tile_z) *tile_z = 32;
+    if (tile_z) *tile_z = kPlanTZ[best.plan];
     if (tile_y) *tile_y = kPlanTY[best.plan];
     if (chunk_x) *chunk_x = best.chunk;
     if (col_group) *col_group = best.group;

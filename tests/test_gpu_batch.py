@@ -98,16 +98,16 @@ def test_autotune_and_launch_choices():
     ref = op.cheb_filter(Xd, 9, *bounds)
     assert op.step_config(binding.SPARC_F32, 5)[:2] == (32, 32)
     tz, ty, cx, cg, cb, us = op.autotune(binding.SPARC_F32, 5)
-    assert us > 0 and (tz, ty) in [(32, 16), (32, 32), (32, 64)] and 1 <= cx <= 30 and 1 <= cg <= 5
+    assert us > 0 and (tz, ty) in [(32, 16), (32, 32), (32, 64), (64, 16), (64, 32)] and 1 <= cx <= 30 and 1 <= cg <= 5
     assert cb in (1, 2)
     assert op.step_config(binding.SPARC_F32, 5) == (tz, ty, cx, cg, cb)
     tuned = op.cheb_filter(Xd, 9, *bounds)
     oref = oracle.cheb_filter(inputs.round_cluster_f32(cl), X, 9, *bounds)
-    for ty in (16, 32, 64):
+    for tzp, ty in ((32, 16), (32, 32), (32, 64), (64, 16), (64, 32)):
         base = None
         for ch, cg, cb in ((0, 0, 1), (8, 1, 2), (16, 3, 1), (30, 8, 2), (0, 2, 2)):
-            op.set_launch(binding.SPARC_F32, 32, ty, ch, cg, cb)
-            assert op.step_config(binding.SPARC_F32, 5)[:2] == (32, ty)
+            op.set_launch(binding.SPARC_F32, tzp, ty, ch, cg, cb)
+            assert op.step_config(binding.SPARC_F32, 5)[:2] == (tzp, ty)
             assert op.step_config(binding.SPARC_F32, 5)[4] == cb
             got = op.cheb_filter(Xd, 9, *bounds)
             if base is None:
@@ -116,9 +116,9 @@ def test_autotune_and_launch_choices():
             g = got.double().cpu().numpy()
             err = (np.linalg.norm(g - oref, axis=1) / np.linalg.norm(oref, axis=1)).max()
             assert err <= 5e-5, (ty, ch, cg, err)
-        if ty == 32:
+        if (tzp, ty) == (32, 32):
             assert torch.equal(base, ref)
-        if ty == tz and ty == 32:
+        if (tzp, ty) == (tz, ty) == (32, 32):
             assert torch.equal(tuned, ref)
     with pytest.raises(binding.SparcError):
         op.set_launch(binding.SPARC_F32, 32, 8, 0)  # 8-row patches are FP64 only

@@ -449,10 +449,12 @@ def test_vector_step_edges(case, dtype):
     rng = np.random.default_rng(sum(n) + ns)
     X = rng.standard_normal((ns, cl.nd))
     if dtype == "f32":
-        tdt, code, tol, heights = torch.float32, binding.SPARC_F32, TOL32, (16, 32, 64)
+        tdt, code, tol, heights = torch.float32, binding.SPARC_F32, TOL32, ((32, 16), (32, 32), (32, 64), (64, 16),
+                                                                            (64, 32))
         X, ocl, pad = inputs.round_to_f32(X), inputs.round_cluster_f32(cl), 4
     else:
-        tdt, code, tol, heights = torch.float64, binding.SPARC_F64, TOL64, (8, 16, 32)
+        tdt, code, tol, heights = torch.float64, binding.SPARC_F64, TOL64, ((32, 8), (32, 16), (32, 32), (64, 8),
+                                                                            (64, 16))
         ocl, pad = cl, 2
     op = binding.Operator(cl)
     big = torch.zeros((ns, cl.nd + 4 * pad), dtype=tdt, device="cuda")
@@ -461,16 +463,16 @@ def test_vector_step_edges(case, dtype):
     a0, a, b = -3.0, 2.0, oracle.upper_bound(cl)
     href = oracle.h_apply(ocl, X)
     fref = oracle.cheb_filter(ocl, X, m, a0, a, b)
-    for ty in heights:
+    for tzp, ty in heights:
         for cb in (1, 2):
-            op.set_launch(code, 32, ty, 0, 0, cb)
-            assert op.step_config(code, ns)[:2] == (32, ty) and op.step_config(code, ns)[4] == cb
+            op.set_launch(code, tzp, ty, 0, 0, cb)
+            assert op.step_config(code, ns)[:2] == (tzp, ty) and op.step_config(code, ns)[4] == cb
             outbig = torch.full((ns, cl.nd + 2 * pad), 7.0, dtype=tdt, device="cuda")
             op.h_apply(Xv, outbig[:, : cl.nd])
             assert rel_err(host(outbig[:, : cl.nd]), href) <= tol, (ty, cb)
             assert torch.all(outbig[:, cl.nd:] == 7.0)  # padding untouched
             e = rel_err(host(op.cheb_filter(Xv, m, a0, a, b)), fref)
-            print(f"{n} {dtype} TY={ty} col_block {cb} filter err {e:.2e}")
+            print(f"{n} {dtype} patch {ty}x{tzp} col_block {cb} filter err {e:.2e}")
             assert e <= tol, (ty, cb)
 
 
