@@ -29,6 +29,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 KSTEPS_LANCZOS = 40
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic_cluster160.txt")
+# launch choices of the autotuner on MI355X for the benchmark clusters (read
+# by the library through SPARC_TUNE_CACHE; a fresh tuning run appends to it),
+# so that the benchmark runs the launch its committed counters were taken on
+TUNE_CACHE = os.path.join(ROOT, "paper_1603_04334_amd", "tune_mi355x.txt")
 STENCIL_SRCS = [os.path.join(ROOT, "paper_1603_04334_amd", "csrc", f)
                 for f in ("fstep.hip", "fstep_kernel.hpp", "fstep_launch.hpp", "nonlocal_kernel.hpp")]
 
@@ -68,9 +72,11 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(dtype):
+def read_traffic(dtype, config=None):
     """Calibrated HBM bytes per recurrence-step launch from committed counter
-    runs, or None when absent or taken on a different kernel source."""
+    runs, or None when absent, taken on a different kernel source, or on
+    another launch configuration than ``config`` (tile_z tile_y chunk_x
+    col_group col_block)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -79,6 +85,8 @@ def read_traffic(dtype):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
     if kv.get("stencil_sha256_16") != source_hash():
+        return None
+    if config is not None and kv.get(f"{dtype}_launch") != " ".join(str(int(v)) for v in config):
         return None
     try:
         return float(kv[f"{dtype}_hbm_bytes_per_launch"])
@@ -370,6 +378,35 @@ def serve_point(setup, rate, nclusters, workers):
             "degree_halvings": int(sum(r["halvings"] for _, _, r in ok))}
 
 
+def serve_sequential_f64(setup):
+    """The same sessions' work without the server: every cluster in FP64,
+    one after another on one stream through the plain library calls
+    (operator, Lanczos bounds, three CheFSI passes, then one pass per later
+    request).  The comparison point for the served throughput."""
+    import torch
+    from paper_1603_04334_amd import binding, inputs
+    torch.cuda.synchronize()
+    upd = 0
+    t0 = time.perf_counter()
+    for sd, c in setup.specs.items():
+        cl = inputs.make_cluster(c["n"], c["h"], c["natoms"], c["zmax"], c["lmax"], sd)
+        op = binding.Operator(cl)
+        X = setup.X64[: cl.nd * c["ns"]].view(c["ns"], cl.nd).clone()
+        _, _, theta = op.lanczos(KSTEPS_LANCZOS, setup.v0[: cl.nd])
+        a0, a, bb = binding.select_bounds(theta, 8, ubound=op.upper_bound())
+        ne = min(c["ne"], 2 * (c["ns"] - 30))
+        cut = a
+        for k in range(SERVE_STEPS):
+            th, lf, deg = op.chefsi(X, c["m"], 3 if k == 0 else 1, ne, a0, cut, bb)
+            cut = float(lf[-1]) + 0.1
+            upd += cl.nd * c["ns"] * int(deg.sum())
+        del X, op
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"what": "the same sessions in FP64, one cluster after another through the library calls, no server",
+            "seconds": dt, "updates_per_s": upd / dt, "requests_per_s": len(setup.specs) * SERVE_STEPS / dt}
+
+
 def serve_measure(rates, nrequests, workers):
     import torch
     from paper_1603_04334_amd import binding
@@ -387,6 +424,8 @@ def serve_measure(rates, nrequests, workers):
                        f"FP32:FP64 = 80:20, Poisson session arrivals at rate/{SERVE_STEPS}, requests chained",
            "workers": workers, "budget_bytes": SERVE_BUDGET, "points": points,
            "cleared_hip_errors": int(binding.lib().sparc_cleared_hip_errors())}
+    print("bench: serving reference (sequential FP64)", file=sys.stderr, flush=True)
+    out["sequential_f64"] = serve_sequential_f64(setup)
     del setup
     torch.cuda.empty_cache()
     return out
@@ -583,6 +622,7 @@ def main():
         print(json.dumps({"error": "bench.py measures one GPU only; runs on several GPUs are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    os.environ.setdefault("SPARC_TUNE_CACHE", TUNE_CACHE)
     import torch
     from paper_1603_04334_amd import binding, inputs
     binding.lib()
@@ -647,7 +687,7 @@ def main():
         "filter_only": {"value": updates / (main_res["filter_ms"] * 1e-3), "ms": main_res["filter_ms"]},
         "stages_ms": main_res["stages_ms"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(args.dtype),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(args.dtype, (tz, ty, cx, cg, cb)),
                      "kernel": "fstep_kernel (vector stencil + local potential + recurrence with Y_{k-1}, with the "
                                "projector gather of Y_k in its last workgroups)",
                      "launches": n_launch, "avg_launch_us": avg_s * 1e6, "alg_bytes_per_launch": alg,
