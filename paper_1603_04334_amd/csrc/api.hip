@@ -324,6 +324,7 @@ int sparc_op_create(const sparc_grid *grid, const double *veff, int32_t natoms, 
         std::vector<int> cur;
         auto close_block = [&](int end_pt) {
             blk_pt.push_back(end_pt);
+            op->nl_max_slots = std::max(op->nl_max_slots, (int)cur.size());
             for (int J : cur) {
                 blk_atoms.push_back(J);
                 slot_of[J] = -1;
@@ -419,6 +420,8 @@ int sparc_op_set_launch(sparc_op *op, int32_t dtype, int32_t tile_z, int32_t til
         for (int p = 0; p < kNumPlans; ++p)
             if (kPlanTZ[p] == tile_z && kPlanTY[p] == tile_y && vec_plan_valid(dtype, p)) found = p;
         if (found < 0) return fail(SPARC_E_ARG, "unsupported tile shape");
+        if (col_block == 2 && vec_max_cblk(dtype, found) < 2)
+            return fail(SPARC_E_ARG, "this tile shape takes one column per workgroup");
         op->tune_shape[dtype] = found;
     }
     op->tune_chunk[dtype] = chunk_x > 0 ? chunk_x : 0;

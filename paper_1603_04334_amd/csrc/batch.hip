@@ -206,7 +206,7 @@ __device__ __forceinline__ void do_scatter(const BatchClusterDev &c, int k, int 
     sa.alpha = (T)c.coef[3 * k];
 #pragma unroll 1
     for (int cg = 0; cg < c.ncg; ++cg) {
-        scatter_item<T>(sa, local, cg, (T(*)[kMaxProj][kScatterCols])smem);
+        scatter_item<T, kScatterCols>(sa, local, cg, (T *)smem, kMaxProj);
         __syncthreads();
     }
 }

@@ -9,9 +9,10 @@
 // alpha V_nl yk (Sec. 3.1 Eq. non-localPS:FD).
 //
 // Data movement (HBM-bound):
-//  * A workgroup owns a TY x TZ patch (TZ = 32 or 64 nodes) of the (y, z)
-//    plane of one column and streams it along x (64-wide patches halve the
-//    share of the z halo, whose two partial lines per row are fetched whole).  Each lane owns one unit of consecutive z nodes of one
+//  * A workgroup owns a TY x TZ patch (TZ = 32, 64, 80 or 160 nodes) of the
+//    (y, z) plane of one column and streams it along x (wider patches cut the
+//    share of the z halo, whose two partial lines per row are fetched whole;
+//    a patch as wide as the grid has none).  Each lane owns one unit of consecutive z nodes of one
 //    y row: 4 FP32 or 2 FP64 values, 16 bytes, so every global access is a
 //    16-byte raw buffer load or store (a plain copy with 4-byte accesses per
 //    lane reaches about 60% of the bandwidth of 16-byte accesses on this
@@ -44,19 +45,25 @@ namespace sparc {
 
 static int vec_width(int dtype) { return dtype == SPARC_F64 ? 2 : 4; }
 
-// patches offered per dtype (TY x TZ): FP64 8, 16, 32 x 32 and 8, 16 x 64;
-// FP32 16, 32, 64 x 32 and 16, 32 x 64 (128 to 512 threads)
+// patches offered per dtype (TY x TZ): FP64 8, 16, 32 x 32 and 8, 16, 24 x 64;
+// FP32 16, 32, 64 x 32, 16, 32 x 64, 32 x 80 and 24 x 160 (128 to 960
+// threads).  The wide ones cut the halo: a 24 x 160 patch spans a whole
+// 160-node row, so it has no z halo at all and a y halo of 12 rows per 24.
 static int vec_default_plan(int dtype) { return dtype == SPARC_F64 ? 1 : 2; }  // 16 x 32 FP64, 32 x 32 FP32
 
 static int vec_nt(int dtype, int plan) { return (kPlanTZ[plan] / vec_width(dtype)) * kPlanTY[plan]; }
 
 bool vec_plan_valid(int dtype, int plan)
 {
-    static const bool f64[kNumPlans] = {true, true, true, false, true, true, false};
-    static const bool f32[kNumPlans] = {false, true, true, true, false, true, true};
+    static const bool f64[kNumPlans] = {true, true, true, false, true, true, false, false, false, true};
+    static const bool f32[kNumPlans] = {false, true, true, true, false, true, true, true, true, false};
     if (plan < 0 || plan >= kNumPlans) return false;
     return dtype == SPARC_F64 ? f64[plan] : f32[plan];
 }
+
+// two columns per workgroup double the register queues: only patches of at
+// most 512 threads (whose waves may use 256 registers) take them
+int vec_max_cblk(int dtype, int plan) { return vec_nt(dtype, plan) <= 512 ? 2 : 1; }
 
 // split x so that about 8192 waves are in flight (at most kMaxChunks chunks,
 // at least 4 planes each)
@@ -93,7 +100,7 @@ FLaunch choose_vec_launch(const sparc_op *op, int dtype, int ns, std::initialize
     L.plan = plan;
     set_chunks(op, nch, L);
     L.cgroup = (tuned && op->tune_group[dtype] > 0) ? op->tune_group[dtype] : 1;
-    L.cblk = (tuned && op->tune_cblk[dtype] == 2) ? 2 : 1;
+    L.cblk = (tuned && op->tune_cblk[dtype] == 2 && vec_max_cblk(dtype, plan) == 2) ? 2 : 1;
     return L;
 }
 
@@ -175,7 +182,11 @@ static int launch_fstep_t(const sparc_op *op, const FLaunch &L, const void *yk, 
     ProfScope prof(prev ? 0 : 3, stream);
     const int natoms = std::max(op->natoms, 1);
     if constexpr (std::is_same<T, float>::value) {
-        if (tz == 64) {
+        if (tz == 160) {
+            if (ty == 24) return fstep_f32_ty24_tz160(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
+        } else if (tz == 80) {
+            if (ty == 32) return fstep_f32_ty32_tz80(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
+        } else if (tz == 64) {
             switch (ty) {
                 case 16: return fstep_f32_ty16_tz64(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
                 case 32: return fstep_f32_ty32_tz64(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
@@ -192,6 +203,7 @@ static int launch_fstep_t(const sparc_op *op, const FLaunch &L, const void *yk, 
             switch (ty) {
                 case 8: return fstep_f64_ty8_tz64(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
                 case 16: return fstep_f64_ty16_tz64(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
+                case 24: return fstep_f64_ty24_tz64(a, g, natoms, ncb, nitems, ngb, prev, strm, cb, stream);
             }
         } else {
             switch (ty) {

@@ -19,11 +19,13 @@ __global__ void __launch_bounds__((TZ / VecTraits<T>::N) * TY)
     constexpr int NT = (TZ / VecTraits<T>::N) * TY;
     if constexpr (TAIL) {
         if ((int)blockIdx.x >= a.nblocks) {
+            // G whole groups of 256 threads; threads past them (NT not a
+            // multiple of 256) only join the items' barrier
             constexpr int G = NT / 256;
             __shared__ T tile[G][4][16][16];
             const int sub = threadIdx.x >> 8;
             const int item = ((int)blockIdx.x - a.nblocks) * G + sub;
-            if (item < nitems)
+            if (sub < G && item < nitems)
                 gather_item<T, T>(g, item % natoms, (item / natoms) % ncb, item / (natoms * ncb), tile[sub],
                                   threadIdx.x & 255);
             else
@@ -80,12 +82,18 @@ int fstep_dispatch_b(const FStepArgs<T> &a, const GatherArgs<T, T> &g, int natom
     return SPARC_OK;
 }
 
-// cblk: columns per workgroup (1 or 2)
+// cblk: columns per workgroup (1 or 2; 2 only for patches of at most 512
+// threads, whose waves can hold two register queues)
 template <typename T, int TY, int TZ = kFTZ>
 int fstep_dispatch(const FStepArgs<T> &a, const GatherArgs<T, T> &g, int natoms, int ncb, int nitems, int ngb,
                    bool prev, bool strm, int cblk, hipStream_t s)
 {
-    if (cblk == 2) return fstep_dispatch_b<T, TY, TZ, 2>(a, g, natoms, ncb, nitems, ngb, prev, strm, s);
+    constexpr int NT = (TZ / VecTraits<T>::N) * TY;
+    if constexpr (NT <= 512) {
+        if (cblk == 2) return fstep_dispatch_b<T, TY, TZ, 2>(a, g, natoms, ncb, nitems, ngb, prev, strm, s);
+    } else {
+        if (cblk == 2) return fail(SPARC_E_ARG, "two columns per workgroup need patches of at most 512 threads");
+    }
     return fstep_dispatch_b<T, TY, TZ, 1>(a, g, natoms, ncb, nitems, ngb, prev, strm, s);
 }
 
@@ -102,6 +110,9 @@ SPARC_FSTEP_DECL(fstep_f32_ty16_tz64, float)
 SPARC_FSTEP_DECL(fstep_f32_ty32_tz64, float)
 SPARC_FSTEP_DECL(fstep_f64_ty8_tz64, double)
 SPARC_FSTEP_DECL(fstep_f64_ty16_tz64, double)
+SPARC_FSTEP_DECL(fstep_f32_ty24_tz160, float)
+SPARC_FSTEP_DECL(fstep_f32_ty32_tz80, float)
+SPARC_FSTEP_DECL(fstep_f64_ty24_tz64, double)
 #undef SPARC_FSTEP_DECL
 
 }  // namespace sparc

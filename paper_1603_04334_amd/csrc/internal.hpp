@@ -31,9 +31,9 @@ struct AtomDev {
 };
 
 // Patches of the vector step kernels: TY x TZ nodes in (y, z) per plan
-constexpr int kNumPlans = 7;
-constexpr int kPlanTY[kNumPlans] = {8, 16, 32, 64, 8, 16, 32};
-constexpr int kPlanTZ[kNumPlans] = {32, 32, 32, 32, 64, 64, 64};
+constexpr int kNumPlans = 10;
+constexpr int kPlanTY[kNumPlans] = {8, 16, 32, 64, 8, 16, 32, 24, 32, 24};
+constexpr int kPlanTZ[kNumPlans] = {32, 32, 32, 32, 64, 64, 64, 160, 80, 64};
 
 // Tile shapes of the fused step kernel: a workgroup of nt threads owns a
 // TY x TZ patch of the (y, z) plane and streams it along x.  TZ lanes run
@@ -75,6 +75,7 @@ struct sparc_op {
     // scatter blocks (node ranges and the atoms each touches)
     int nl_npts = 0;
     int nl_nblk = 0;
+    int nl_max_slots = 0;  // most atoms one scatter block touches
     int *d_nl_pts = nullptr;
     int *d_nl_off = nullptr;
     int *d_nl_ent = nullptr;  // int4 records
@@ -153,6 +154,7 @@ constexpr int kMaxChunks = 16;  // most x-chunks of a vector step launch
 
 // is plan a patch height offered for dtype
 bool vec_plan_valid(int dtype, int plan);
+int vec_max_cblk(int dtype, int plan);  // columns per workgroup the plan's patch can hold (1 or 2)
 // vector launch for a block of ns columns whose leading dimensions are lds
 FLaunch choose_vec_launch(const sparc_op *op, int dtype, int ns, std::initializer_list<int64_t> lds);
 // the default x split of patch height `plan` (no tuning applied)

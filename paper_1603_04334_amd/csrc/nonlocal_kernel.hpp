@@ -110,7 +110,7 @@ __device__ __forceinline__ void gather_item(const GatherArgs<T, TI> &g, int atom
     }
 }
 
-constexpr int kScatterCols = 8;  // columns per scatter workgroup (the table of h^3 gamma S is built once for them)
+constexpr int kScatterCols = 8;  // columns per scatter item of the batched kernel
 
 template <typename T>
 struct ScatterArgs {
@@ -131,31 +131,37 @@ struct ScatterArgs {
     T alpha;
 };
 
-template <typename T>
-__device__ __forceinline__ void scatter_item(const ScatterArgs<T> &s, int b, int cg, T (*gl)[kMaxProj][kScatterCols])
+// One node block b (at most 256 nodes) and NC columns from cg * NC.  gl: the
+// block's table h^3 gamma S, [slot][npm][NC] (npm >= every atom's projector
+// count).  The out values of all NC columns are requested before the table
+// is built, so their latency overlaps it.  Per node and column the sum runs
+// over the node's entries and projectors in table order whatever NC is, so
+// every column count gives the same bits.
+template <typename T, int NC>
+__device__ __forceinline__ void scatter_item(const ScatterArgs<T> &s, int b, int cg, T *gl, int npm)
 {
-    const int c0 = cg * kScatterCols;
+    const int c0 = cg * NC;
     const int a0 = s.blk_at[b];
     const int na = s.blk_at[b + 1] - a0;
     const long long split = (long long)s.nproj_total * s.ns;
-    // this thread's node: its output values and first entry are requested
-    // before the table is built, so their latency overlaps it
     const int pi = s.blk_pt[b] + threadIdx.x;
     const bool own = pi < s.blk_pt[b + 1];
     int gpt = 0, e0 = 0, e1 = 0;
-    T cur[kScatterCols] = {};
+    T cur[NC];
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) cur[cc] = T(0);
     if (own) {
         gpt = s.pts[pi];
         e0 = s.ent_off[pi];
         e1 = s.ent_off[pi + 1];
 #pragma unroll
-        for (int cc = 0; cc < kScatterCols; ++cc)
+        for (int cc = 0; cc < NC; ++cc)
             if (c0 + cc < s.ns) cur[cc] = s.out[(long long)(c0 + cc) * s.ldo + gpt];
     }
-    for (int idx = threadIdx.x; idx < na * kMaxProj * kScatterCols; idx += 256) {
-        const int slot = idx / (kMaxProj * kScatterCols);
-        const int p = (idx / kScatterCols) % kMaxProj;
-        const int cc = idx % kScatterCols;
+    for (int idx = threadIdx.x; idx < na * npm * NC; idx += 256) {
+        const int slot = idx / (npm * NC);
+        const int p = (idx / NC) % npm;
+        const int cc = idx % NC;
         const AtomDev A = s.atoms[s.blk_atoms[a0 + slot]];
         T v = T(0);
         if (p < A.nproj && c0 + cc < s.ns) {
@@ -165,21 +171,24 @@ __device__ __forceinline__ void scatter_item(const ScatterArgs<T> &s, int b, int
             for (int q = 0; q < kGatherSplit; ++q) sum += s.part[q * split + pg * s.ns + c0 + cc];
             v = s.hg[pg] * sum;
         }
-        gl[slot][p][cc] = v;
+        gl[idx] = v;
     }
     __syncthreads();
     if (!own) return;
-    T acc[kScatterCols] = {};
+    T acc[NC];
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc) acc[cc] = T(0);
     for (int e = e0; e < e1; ++e) {
         const int4 en = s.ent[e];
         for (int p = 0; p < en.w; ++p) {
             const T cv = s.chi[en.x + (long long)p * en.y];
+            const T *row = gl + (en.z * npm + p) * NC;
 #pragma unroll
-            for (int cc = 0; cc < kScatterCols; ++cc) acc[cc] += cv * gl[en.z][p][cc];
+            for (int cc = 0; cc < NC; ++cc) acc[cc] += cv * row[cc];
         }
     }
 #pragma unroll
-    for (int cc = 0; cc < kScatterCols; ++cc)
+    for (int cc = 0; cc < NC; ++cc)
         if (c0 + cc < s.ns) s.out[(long long)(c0 + cc) * s.ldo + gpt] = cur[cc] + s.alpha * acc[cc];
 }
 

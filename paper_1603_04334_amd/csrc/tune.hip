@@ -132,7 +132,7 @@ extern "C" int sparc_autotune(sparc_op *op, int32_t dtype, int32_t ns, void *str
                 for (int cb = 1; cb <= 2 && st == SPARC_OK; ++cb) {
                 for (int gi = 0; gi < 4 && st == SPARC_OK; ++gi) {
                     if (groups[gi] * cb > ns && gi > 0) continue;
-                    if (cb == 2 && ns < 2) continue;
+                    if (cb == 2 && (ns < 2 || vec_max_cblk(dtype, p) < 2)) continue;
                     op->tune_shape[dtype] = p;
                     op->tune_chunk[dtype] = chunks[ci];
                     op->tune_group[dtype] = groups[gi];

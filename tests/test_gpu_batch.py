@@ -20,6 +20,9 @@ JOBS = [
     ((26, 20, 24), 0.45, 3, 1, 33, 8, torch.float64),
 ]
 
+# FP32 patches (tile_z, tile_y) of the vector step
+SHAPES32 = [(32, 16), (32, 32), (32, 64), (64, 16), (64, 32), (80, 32), (160, 24)]
+
 
 def _setup():
     from paper_1603_04334_amd import binding
@@ -98,14 +101,16 @@ def test_autotune_and_launch_choices():
     ref = op.cheb_filter(Xd, 9, *bounds)
     assert op.step_config(binding.SPARC_F32, 5)[:2] == (32, 32)
     tz, ty, cx, cg, cb, us = op.autotune(binding.SPARC_F32, 5)
-    assert us > 0 and (tz, ty) in [(32, 16), (32, 32), (32, 64), (64, 16), (64, 32)] and 1 <= cx <= 30 and 1 <= cg <= 5
+    assert us > 0 and (tz, ty) in SHAPES32 and 1 <= cx <= 30 and 1 <= cg <= 5
     assert cb in (1, 2)
     assert op.step_config(binding.SPARC_F32, 5) == (tz, ty, cx, cg, cb)
     tuned = op.cheb_filter(Xd, 9, *bounds)
     oref = oracle.cheb_filter(inputs.round_cluster_f32(cl), X, 9, *bounds)
-    for tzp, ty in ((32, 16), (32, 32), (32, 64), (64, 16), (64, 32)):
+    for tzp, ty in SHAPES32:
         base = None
         for ch, cg, cb in ((0, 0, 1), (8, 1, 2), (16, 3, 1), (30, 8, 2), (0, 2, 2)):
+            if (tzp // 4) * ty > 512:
+                cb = 1  # one column per workgroup on patches of more than 512 threads
             op.set_launch(binding.SPARC_F32, tzp, ty, ch, cg, cb)
             assert op.step_config(binding.SPARC_F32, 5)[:2] == (tzp, ty)
             assert op.step_config(binding.SPARC_F32, 5)[4] == cb
@@ -124,3 +129,5 @@ def test_autotune_and_launch_choices():
         op.set_launch(binding.SPARC_F32, 32, 8, 0)  # 8-row patches are FP64 only
     with pytest.raises(binding.SparcError):
         op.set_launch(binding.SPARC_F32, 32, 32, 0, 0, 3)  # one or two columns per workgroup
+    with pytest.raises(binding.SparcError):
+        op.set_launch(binding.SPARC_F32, 160, 24, 0, 0, 2)  # 960 threads: one column per workgroup

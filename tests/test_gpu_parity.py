@@ -434,6 +434,8 @@ VEC = [
     ((5, 40, 64), 0.5, 2, 1, 2, 6, 4),
     ((33, 24, 8), 0.6, 1, 1, 4, 4, 5),
     ((18, 18, 20), 0.5, 2, 2, 1, 6, 7),
+    # z extent above the widest patch (160 nodes): a full and a ragged z patch
+    ((6, 30, 172), 0.5, 2, 1, 2, 6, 4),
 ]
 
 
@@ -450,11 +452,11 @@ def test_vector_step_edges(case, dtype):
     X = rng.standard_normal((ns, cl.nd))
     if dtype == "f32":
         tdt, code, tol, heights = torch.float32, binding.SPARC_F32, TOL32, ((32, 16), (32, 32), (32, 64), (64, 16),
-                                                                            (64, 32))
+                                                                            (64, 32), (80, 32), (160, 24))
         X, ocl, pad = inputs.round_to_f32(X), inputs.round_cluster_f32(cl), 4
     else:
         tdt, code, tol, heights = torch.float64, binding.SPARC_F64, TOL64, ((32, 8), (32, 16), (32, 32), (64, 8),
-                                                                            (64, 16))
+                                                                            (64, 16), (64, 24))
         ocl, pad = cl, 2
     op = binding.Operator(cl)
     big = torch.zeros((ns, cl.nd + 4 * pad), dtype=tdt, device="cuda")
@@ -464,7 +466,12 @@ def test_vector_step_edges(case, dtype):
     href = oracle.h_apply(ocl, X)
     fref = oracle.cheb_filter(ocl, X, m, a0, a, b)
     for tzp, ty in heights:
-        for cb in (1, 2):
+        # patches of more than 512 threads take one column per workgroup
+        wide = (tzp // pad) * ty > 512
+        if wide:
+            with pytest.raises(binding.SparcError):
+                op.set_launch(code, tzp, ty, 0, 0, 2)
+        for cb in ((1,) if wide else (1, 2)):
             op.set_launch(code, tzp, ty, 0, 0, cb)
             assert op.step_config(code, ns)[:2] == (tzp, ty) and op.step_config(code, ns)[4] == cb
             outbig = torch.full((ns, cl.nd + 2 * pad), 7.0, dtype=tdt, device="cuda")
