@@ -250,7 +250,8 @@ def batch_measure(reps=5, nclusters=64):
     out = {"workload": f"{nclusters} uneven clusters, grid edge 32-96, h=0.45, 16-128 orbitals, degree 16-28",
            "updates_per_run": work}
     for name, jobs, mode in (("persistent_graph_f32", jobs32, 0), ("grouped_levels_graph_f32", jobs32, 4),
-                             ("sequential_f32", jobs32, 3), ("sequential_f64", jobs64, 3)):
+                             ("concurrent_streams_f32", jobs32, 5), ("sequential_f32", jobs32, 3),
+                             ("sequential_f64", jobs64, 3)):
         bt = binding.Batch(jobs, mode=mode)
         bt.run()
         if bt.check():
@@ -267,8 +268,10 @@ def batch_measure(reps=5, nclusters=64):
         if mode == 0:
             out["items"], out["levels"], out["grid"] = bt.info()
         bt.close()
-    for k in ("persistent_graph_f32", "grouped_levels_graph_f32", "sequential_f32"):
+    for k in ("persistent_graph_f32", "grouped_levels_graph_f32", "concurrent_streams_f32", "sequential_f32"):
         out[k]["vs_sequential_f64"] = out[k]["value"] / out["sequential_f64"]["value"]
+    for k in ("persistent_graph_f32", "grouped_levels_graph_f32", "concurrent_streams_f32"):
+        out[k]["vs_sequential_f32"] = out[k]["value"] / out["sequential_f32"]["value"]
     return out
 
 

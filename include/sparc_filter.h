@@ -373,7 +373,12 @@ typedef struct sparc_batch sparc_batch;
  *   mode 1: the same persistent launch without the graph;
  *   mode 2: one grouped launch per level (no waits);
  *   mode 3: the plain filters one after another;
- *   mode 4: mode 2 captured in a HIP graph (replayed on later runs).
+ *   mode 4: mode 2 captured in a HIP graph (replayed on later runs);
+ *   mode 5: the plain filters on four streams owned by the batch (jobs dealt
+ *           longest first to the least loaded one), started after the work
+ *           already on `stream` and joined back to it by events; the
+ *           filters of different jobs overlap.  Each job still runs on one
+ *           stream with its own workspace.
  * Every mode gives each job exactly the result of sparc_cheb_filter.
  * Allocates the per-job workspaces and the schedule on the current device.
  * Errors: SPARC_E_ARG, SPARC_E_BOUNDS, SPARC_E_SHAPE, SPARC_E_NOMEM, SPARC_E_HIP. */

@@ -282,12 +282,14 @@ class Operator:
               "sparc_cheb_filter")
         return Y
 
-    def lanczos(self, k: int, v0, stream=None):
+    def lanczos(self, k: int, v0, stream=None, ws=None):
         import torch
         if v0.dtype != torch.float64 or v0.numel() != self.nd or not v0.is_cuda:
             raise ValueError("v0 must be a device float64 vector of N_d values")
         nb = int(lib().sparc_lanczos_workspace_bytes(self.handle, k))
-        ws = torch.empty(nb, dtype=torch.uint8, device=v0.device)
+        if ws is None:
+            ws = torch.empty(nb, dtype=torch.uint8, device=v0.device)
+        nb = ws.numel()
         alpha = np.zeros(k)
         beta = np.zeros(max(k - 1, 1))
         theta = np.zeros(k)
@@ -489,7 +491,7 @@ class Batch:
     jobs: sequence of (Operator, X, Y, m, a0, a, b) with X, Y device blocks of
     the same dtype.  mode: 0 persistent + HIP graph, 1 persistent, 2 one grouped
     launch per level, 3 the plain filters one after another, 4 mode 2 in a HIP
-    graph."""
+    graph, 5 the plain filters on the batch's four streams."""
 
     def __init__(self, jobs, mode: int = 0):
         arr = (sparc_batch_job * len(jobs))()

@@ -27,7 +27,12 @@
 // (replayed on later runs); 1 = the same two launches without a graph;
 // 2 = one grouped launch per level (kernel boundaries as barriers, no waits);
 // 3 = the plain per-cluster filters one after another (reference);
-// 4 = mode 2 captured in a HIP graph.
+// 4 = mode 2 captured in a HIP graph; 5 = the plain per-cluster filters
+// (their tuned launches) on kBatchLanes streams of the batch, jobs dealt
+// longest first to the least loaded stream, joined to the caller's stream
+// by events: one cluster's launch tails and the gaps between its dependent
+// launches overlap another's work.  Each job runs on one stream with its own
+// workspace, so its result does not depend on the interleaving.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -64,6 +69,8 @@ struct BatchClusterDev {
     const double *coef;  // per step: alpha, beta, shift
     int *cntA, *cntB;    // per-step completion counters
 };
+
+constexpr int kBatchLanes = 4;  // streams of the concurrent mode (the process's default hardware queues)
 
 struct BatchSegment {
     long long start;
@@ -352,6 +359,11 @@ struct sparc_batch {
     hipStream_t cap = nullptr;  // capture stream (the null stream cannot be captured)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // mode 5: the batch's streams, one join event each plus the start event,
+    // and the stream of every job
+    hipStream_t lane[kBatchLanes] = {};
+    hipEvent_t lane_ev[kBatchLanes + 1] = {};
+    std::vector<int> lane_of;
 };
 
 namespace {
@@ -402,7 +414,7 @@ extern "C" {
 
 int sparc_batch_create(const sparc_batch_job *jobs, int32_t njobs, int32_t mode, sparc_batch **out)
 {
-    if (!jobs || njobs < 1 || !out || mode < 0 || mode > 4) return fail(SPARC_E_ARG, "bad batch arguments");
+    if (!jobs || njobs < 1 || !out || mode < 0 || mode > 5) return fail(SPARC_E_ARG, "bad batch arguments");
     *out = nullptr;
     sparc_batch *b = new (std::nothrow) sparc_batch();
     if (!b) return fail(SPARC_E_NOMEM, "host allocation failed");
@@ -450,6 +462,9 @@ int sparc_batch_create(const sparc_batch_job *jobs, int32_t njobs, int32_t mode,
     if (hipMalloc(&b->d_ints, b->nints * sizeof(int)) != hipSuccess ||
         hipMalloc(&b->d_coef, ncoef * sizeof(double)) != hipSuccess)
         return cleanup(fail(SPARC_E_NOMEM, "device allocation of batch counters failed"));
+    // the abort flag reads zero also in the modes that never reset it
+    if (hipMemset(b->d_ints, 0, b->nints * sizeof(int)) != hipSuccess)
+        return cleanup(fail(SPARC_E_HIP, "clearing the batch counters failed"));
     std::vector<double> coef(ncoef);
     long long cpos = 0;
     b->host_cl.resize(njobs);
@@ -490,7 +505,7 @@ int sparc_batch_create(const sparc_batch_job *jobs, int32_t njobs, int32_t mode,
         c.G = (char *)b->d_work + goff[i];
         // stencil geometry: the dtype's 256-thread vector patch and the
         // standalone filter's x split for it
-        if (mode != 3) {
+        if (mode != 3 && mode != 5) {
             const FLaunch V = choose_vec_launch(op, j.dtype, j.ns, {j.ldx, j.ldy, op->nd});
             if (V.plan < 0)
                 return cleanup(fail(SPARC_E_SHAPE, "job " + std::to_string(i) +
@@ -576,6 +591,30 @@ int sparc_batch_create(const sparc_batch_job *jobs, int32_t njobs, int32_t mode,
         oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<true, false>, kBatchNT, 0);
     if (oe != hipSuccess || per_cu < 1) per_cu = 1;
     b->grid = std::max(1, cus * per_cu);
+    if (mode == 5) {
+        for (int l = 0; l < kBatchLanes; ++l)
+            if (hipStreamCreateWithFlags(&b->lane[l], hipStreamNonBlocking) != hipSuccess)
+                return cleanup(fail(SPARC_E_HIP, "stream creation failed"));
+        for (int l = 0; l <= kBatchLanes; ++l)
+            if (hipEventCreateWithFlags(&b->lane_ev[l], hipEventDisableTiming) != hipSuccess)
+                return cleanup(fail(SPARC_E_HIP, "event creation failed"));
+        // longest first to the least loaded stream (work ~ N_d N_s m bytes)
+        std::vector<int> order(njobs);
+        for (int i = 0; i < njobs; ++i) order[i] = i;
+        auto cost = [&](int i) {
+            return (double)jobs[i].op->nd * jobs[i].ns * jobs[i].m * elem_size(jobs[i].dtype);
+        };
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
+        double load[kBatchLanes] = {};
+        b->lane_of.assign(njobs, 0);
+        for (int i : order) {
+            int l = 0;
+            for (int q = 1; q < kBatchLanes; ++q)
+                if (load[q] < load[l]) l = q;
+            b->lane_of[i] = l;
+            load[l] += cost(i);
+        }
+    }
     *out = b;
     return SPARC_OK;
 }
@@ -584,6 +623,26 @@ int sparc_batch_run(sparc_batch *b, void *stream)
 {
     if (!b) return fail(SPARC_E_ARG, "batch is NULL");
     hipStream_t s = (hipStream_t)stream;
+    if (b->mode == 5) {
+        // the batch's streams start after the caller's stream's earlier work
+        // and the caller's stream waits for all of them
+        SPARC_HIP(hipEventRecord(b->lane_ev[kBatchLanes], s));
+        for (int l = 0; l < kBatchLanes; ++l) SPARC_HIP(hipStreamWaitEvent(b->lane[l], b->lane_ev[kBatchLanes], 0));
+        int st = SPARC_OK;
+        for (int i = 0; i < b->njobs && !st; ++i) {
+            const sparc_batch_job &j = b->jobs[i];
+            const size_t need = sparc_workspace_bytes(j.op, j.dtype, j.ns, 1);
+            st = sparc_cheb_filter(j.op, j.dtype, j.X, j.ldx, j.Y, j.ldy, j.ns, j.m, j.a0, j.a, j.b, b->host_cl[i].G,
+                                   need, b->lane[b->lane_of[i]]);
+        }
+        // join every stream, also after a failed submission
+        for (int l = 0; l < kBatchLanes; ++l) {
+            if (hipEventRecord(b->lane_ev[l], b->lane[l]) != hipSuccess ||
+                hipStreamWaitEvent(s, b->lane_ev[l], 0) != hipSuccess)
+                if (!st) st = fail(SPARC_E_HIP, "joining the batch streams failed");
+        }
+        return st;
+    }
     if (b->mode == 3) {
         // reference: the plain filters one after another on the stream
         for (int i = 0; i < b->njobs; ++i) {
@@ -644,6 +703,14 @@ int sparc_batch_destroy(sparc_batch *b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (int l = 0; l < kBatchLanes; ++l) {
+        if (b->lane[l]) {
+            (void)hipStreamSynchronize(b->lane[l]);
+            (void)hipStreamDestroy(b->lane[l]);
+        }
+    }
+    for (int l = 0; l <= kBatchLanes; ++l)
+        if (b->lane_ev[l]) (void)hipEventDestroy(b->lane_ev[l]);
     (void)hipFree(b->d_cl);
     (void)hipFree(b->d_seg);
     (void)hipFree(b->d_ints);

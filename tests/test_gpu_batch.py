@@ -45,12 +45,12 @@ def _setup():
     return binding, jobs
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3, 4, 5])
 def test_batch_bitwise_equals_standalone(mode):
     binding, jobs = _setup()
     outs = [torch.full_like(j["Xd"], float("nan")) for j in jobs]
     batch = binding.Batch([(j["op"], j["Xd"], o, j["m"], *j["bounds"]) for j, o in zip(jobs, outs)], mode=mode)
-    for rep in range(2):  # the second run replays the captured graph in mode 0
+    for rep in range(2):  # the second run replays the captured graph in modes 0 and 4
         for o in outs:
             o.fill_(float("nan"))
         batch.run()
@@ -59,7 +59,7 @@ def test_batch_bitwise_equals_standalone(mode):
         for j, o in zip(jobs, outs):
             assert torch.equal(o, j["ref"]), (mode, rep, j["cl"].n)
     items, levels, grid = batch.info()
-    if mode != 3:
+    if mode not in (3, 5):
         # per degree step: gather and stencil items, then scatter items
         assert items > 0 and levels == 2 * max(j["m"] for j in jobs)
     batch.close()
