@@ -299,7 +299,9 @@ class ServeSetup:
         self.v0 = inputs.device_orbitals(maxnd, 1, 6, torch.float64).view(-1)
         torch.cuda.synchronize()
         self.descs = {}
-        for sd, c in specs.items():
+        for i, (sd, c) in enumerate(specs.items()):
+            if i % 50 == 0:
+                print(f"serving setup: cluster {i} of {len(specs)}", file=sys.stderr, flush=True)
             cl = inputs.make_cluster(c["n"], c["h"], c["natoms"], c["zmax"], c["lmax"], sd)
             src = self.X32 if c["fp32"] else self.X64
             X0 = src[: cl.nd * c["ns"]].view(c["ns"], cl.nd)
@@ -391,7 +393,9 @@ def serve_sequential_f64(setup):
     torch.cuda.synchronize()
     upd = 0
     t0 = time.perf_counter()
-    for sd, c in setup.specs.items():
+    for i, (sd, c) in enumerate(setup.specs.items()):
+        if i % 50 == 0:
+            print(f"serving reference: cluster {i} of {len(setup.specs)}", file=sys.stderr, flush=True)
         cl = inputs.make_cluster(c["n"], c["h"], c["natoms"], c["zmax"], c["lmax"], sd)
         op = binding.Operator(cl)
         X = setup.X64[: cl.nd * c["ns"]].view(c["ns"], cl.nd).clone()
@@ -401,7 +405,14 @@ def serve_sequential_f64(setup):
         cut = a
         for k in range(SERVE_STEPS):
             th, lf, deg = op.chefsi(X, c["m"], 3 if k == 0 else 1, ne, a0, cut, bb)
+            # the library's rule between passes: a cutoff at or below a0 lowers
+            # a0 to the last pass's lowest Ritz value
+            for p in range(th.shape[0] - 1):
+                if lf[p] + 0.1 <= a0:
+                    a0 = float(th[p][0])
             cut = float(lf[-1]) + 0.1
+            if cut <= a0:
+                a0 = float(th[-1][0])
             upd += cl.nd * c["ns"] * int(deg.sum())
         del X, op
     torch.cuda.synchronize()
@@ -450,6 +461,8 @@ def secondary(args):
         p.step()
         ms = timed(p.filter_only, 20, 2) * 1e3
         med[f"filter_{dt}"] = {"ms": ms, "value": cl.nd * c.ns * c.m / (ms * 1e-3)}
+        if dt == "f64":
+            out["_full_medium"] = (c, cl, op, p.bounds)
         del p
     out["medium"] = med
     c = inputs.SMALL
@@ -457,6 +470,7 @@ def secondary(args):
     op = binding.Operator(cl)
     p = Pass(c, cl, op, "f64", tune=False)
     p.step()
+    out["_full_small"] = (c, cl, op, p.bounds)
     step_ms = timed(p.step, 20, 3) * 1e3
     filt_ms = timed(p.filter_only, 50, 3) * 1e3
     out["small_latency"] = {"workload": c.name, "pass_ms": step_ms, "filter_ms": filt_ms,
@@ -619,6 +633,35 @@ def cpu_baseline(case, cl, op, bounds, ncols=16):
     return out
 
 
+def cpu_full_run(case, cl, op, bounds):
+    """The C oracle's FP64 filter of a whole (small) workload on the host's
+    threads, with the FP64 filter of the same block on the GPU compared
+    column by column."""
+    import torch
+    import oracle
+    from paper_1603_04334_amd import inputs
+    a0, a, b = bounds
+    X = inputs.device_orbitals(cl.nd, case.ns, case.seed, torch.float64)
+    Xh = X.cpu().numpy()
+    t0 = time.perf_counter()
+    ref = oracle.cheb_filter(cl, Xh, case.m, a0, a, b)
+    dt = time.perf_counter() - t0
+    y = op.cheb_filter(X, case.m, a0, a, b).cpu().numpy()
+    err = float((np.linalg.norm(y - ref, axis=1) / np.linalg.norm(ref, axis=1)).max())
+    return {"workload": case.name, "updates": cl.nd * case.ns * case.m, "seconds": dt,
+            "value": cl.nd * case.ns * case.m / dt, "gpu_fp64_max_rel_err": err}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -714,9 +757,12 @@ def main():
         print("bench: first SCF iteration, density, forces, electrostatic potential", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         out["next_rows"] = next_rows(case, cl, op, args.dtype)
+    full = []
     if not args.no_secondary and args.workload == "large":
         print("bench: medium and small clusters", file=sys.stderr, flush=True)
-        out.update(secondary(args))
+        sec = secondary(args)
+        full = [sec.pop("_full_small"), sec.pop("_full_medium")]
+        out.update(sec)
     if not args.no_batch:
         print("bench: batched clusters", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
@@ -729,6 +775,10 @@ def main():
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(case, cl, op, main_res["bounds"],
                                            ncols=16 if args.workload == "large" else min(case.ns, 16))
+        out["cpu_baseline"]["cpu_model"] = cpu_model()
+        out["cpu_baseline"]["host_cpus"] = os.cpu_count()
+        # the small and medium clusters in full (same bounds as their GPU passes)
+        out["cpu_baseline"]["full_runs"] = [cpu_full_run(*f) for f in full]
     print(json.dumps(out), flush=True)
 
 

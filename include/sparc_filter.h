@@ -324,7 +324,11 @@ size_t sparc_chefsi_workspace_bytes(const sparc_op *op, int32_t dtype, int32_t n
  * SCF iteration of a calculation runs about three passes from a random block
  * (Sec. 3.4, last paragraph), every later one a single pass.  The first pass
  * uses the cutoff a; every later pass the previous pass's Fermi level + 0.1 Ha
- * (Sec. 4).  a0 and b are fixed (H does not change between the passes).
+ * (Sec. 4).  b is fixed (H does not change between the passes); so is a0,
+ * except that when a later cutoff falls at or below it (the Lanczos estimate
+ * of lambda_1 had missed a low state) a0 becomes the lowest Ritz value of the
+ * previous pass; a0 only scales the filter's output.  A caller chaining
+ * calls applies the same rule with the theta it received.
  * A pass whose filtered block is numerically rank deficient (the Cholesky
  * factorisation of M_s fails) is filtered again from the same X at half the
  * degree, down to degree 1; degrees reports the degree each pass used.

@@ -430,25 +430,33 @@ def chefsi_passes(cluster, X: np.ndarray, m, passes: int, ne: float, a0: float, 
     """``passes`` CheFSI steps on the orbital block X (Sec. 3.4): filter with
     bounds (a0, cutoff, b), Rayleigh-Ritz, Fermi level of the Ritz values,
     rotation.  The first pass uses the cutoff ``a``; each later pass the
-    previous pass's Fermi level plus ``shift`` (Sec. 4).  a0 and b (lambda_1
-    and lambda_Nd of Alg. 2) stay fixed: without a density update H does not
-    change between the passes of the first SCF iteration (Sec. 3.4, last
-    paragraph).  m: one degree for every pass, or a sequence of per-pass
-    degrees.  Returns (rotated block, list of per-pass dicts with the cutoff,
-    degree, Ritz values and Fermi level)."""
+    previous pass's Fermi level plus ``shift`` (Sec. 4).  b (lambda_Nd of
+    Alg. 2) stays fixed: without a density update H does not change between
+    the passes of the first SCF iteration (Sec. 3.4, last paragraph).  a0
+    (lambda_1 of Alg. 2) stays fixed too, unless a cutoff falls at or below
+    it: the Lanczos estimate of lambda_1 was then too high, and a0 becomes
+    the lowest Ritz value of the previous pass (also an upper bound of
+    lambda_1, below that pass's Fermi level).  a0 only scales the filter's
+    output, so the filtered subspace and the Ritz values do not depend on it.
+    m: one degree for every pass, or a sequence of per-pass degrees.  Returns
+    (rotated block, list of per-pass dicts with a0, the cutoff, degree, Ritz
+    values and Fermi level)."""
     degrees = [int(m)] * passes if np.isscalar(m) else [int(d) for d in m]
     if len(degrees) != passes:
         raise ValueError("one degree per pass")
     X = _block(X, cluster.nd)
     cutoff = float(a)
+    a0 = float(a0)
     record = []
     for p in range(passes):
         Y = cheb_filter(cluster, X, degrees[p], a0, cutoff, b, bc=bc)
         theta, vec, _, _ = rayleigh_ritz(cluster, Y, bc)
         lf = fermi_level(theta, ne, kT)
         X = rotate(Y, vec)
-        record.append(dict(cutoff=cutoff, degree=degrees[p], theta=theta, lambda_f=lf))
+        record.append(dict(a0=a0, cutoff=cutoff, degree=degrees[p], theta=theta, lambda_f=lf))
         cutoff = lf + shift
+        if cutoff <= a0:
+            a0 = float(theta[0])
     return X, record
 
 

@@ -8,8 +8,13 @@
 // between (Sec. 3.4, last paragraph); every later SCF iteration runs one
 // pass.  The cutoff of a pass is the previous pass's Fermi level plus 0.1 Ha
 // (Sec. 4); the first pass takes the caller's cutoff (from the Lanczos
-// bounds).  a0 and b stay fixed: H does not change while the density is not
-// updated.
+// bounds).  b stays fixed: H does not change while the density is not
+// updated.  a0 (the estimate of lambda_1) stays fixed unless a cutoff falls at
+// or below it, which happens when the Lanczos estimate had not converged on a
+// low state the filtered block then found: a0 becomes the lowest Ritz value
+// of the previous pass (an upper bound of lambda_1 below that pass's Fermi
+// level).  a0 only scales the filter's output, so the filtered subspace and
+// the Ritz values do not depend on it.
 //
 // The passes are the paper's guard against rank loss: one filter of high
 // degree concentrates every column on the lowest eigenvectors until the block
@@ -51,7 +56,7 @@ ChefsiLayout chefsi_layout(const sparc_op *op, int dtype, int ns)
 }  // namespace
 
 int chefsi_run(const sparc_op *op, int dtype, void *X, int64_t ldx, int ns, int m, int passes, double ne, double kT,
-               double a0, double a, double b, const ChefsiBuffers &B, double *theta, double *lambda_f,
+               double &a0, double a, double b, const ChefsiBuffers &B, double *theta, double *lambda_f,
                int32_t *degrees, double *rho, hipStream_t s, int *halvings)
 {
     if (passes < 1) return fail(SPARC_E_ARG, "passes must be >= 1");
@@ -64,6 +69,7 @@ int chefsi_run(const sparc_op *op, int dtype, void *X, int64_t ldx, int ns, int 
     for (int p = 0; p < passes; ++p) {
         if (p > 0) {
             cut = lf + kCutoffShift;
+            if (cut <= a0) a0 = th[0];  // th: the previous pass's Ritz values
             if (!(a0 < cut && cut < b))
                 return fail(SPARC_E_BOUNDS, "cutoff from the Fermi level leaves the filter interval (a0, b)");
         }
@@ -137,6 +143,7 @@ extern "C" int sparc_chefsi(const sparc_op *op, int32_t dtype, void *X, int64_t 
     B.rot_bytes = L.rot;
     p += L.rot;
     B.occ = (double *)p;
-    return chefsi_run(op, dtype, X, ldx, ns, m, passes, ne, kT, a0, a, b, B, theta, lambda_f, degrees, rho,
+    double a0w = a0;
+    return chefsi_run(op, dtype, X, ldx, ns, m, passes, ne, kT, a0w, a, b, B, theta, lambda_f, degrees, rho,
                       (hipStream_t)stream, nullptr);
 }

@@ -231,11 +231,13 @@ struct ChefsiBuffers {
 // `passes` CheFSI passes on X in place (filter, Rayleigh-Ritz, Fermi level,
 // rotation); the cutoff of every pass after the first is the previous Fermi
 // level + 0.1 Ha; a pass whose block turns out rank deficient is redone at
-// half the degree.  theta (passes x ns), lambda_f, degrees: host outputs
-// (may be null); rho: device density of the final block (may be null);
-// halvings: number of degree halvings (may be null).  Synchronous.
+// half the degree.  a0: in, the lambda_1 estimate; out, lowered to a pass's
+// lowest Ritz value where a cutoff fell at or below it.  theta (passes x ns),
+// lambda_f, degrees: host outputs (may be null); rho: device density of the
+// final block (may be null); halvings: number of degree halvings (may be
+// null).  Synchronous.
 int chefsi_run(const sparc_op *op, int dtype, void *X, int64_t ldx, int ns, int m, int passes, double ne, double kT,
-               double a0, double a, double b, const ChefsiBuffers &B, double *theta, double *lambda_f,
+               double &a0, double a, double b, const ChefsiBuffers &B, double *theta, double *lambda_f,
                int32_t *degrees, double *rho, hipStream_t s, int *halvings);
 
 // profiling hooks (no-ops unless enabled)

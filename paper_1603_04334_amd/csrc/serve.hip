@@ -51,6 +51,7 @@ struct Cluster {
     std::vector<AtomCopy> atoms;
     int dtype = 0, ns = 0, m = 0;
     double ne = 0, lambda_f = 0;  // electron count; Fermi level of the last pass
+    double theta0 = 0;            // lowest Ritz value of the last pass
     const void *X0 = nullptr;
     int64_t ldx0 = 0;
     const double *v0 = nullptr;
@@ -163,6 +164,7 @@ int execute(sparc_server *srv, Cluster &c, const Request &r, hipStream_t s, spar
     int st;
     int passes = 1;
     double cut = c.lambda_f + 0.1;  // Sec. 4: previous Fermi level + 0.1 Ha
+    if (c.resident && cut <= c.a0) c.a0 = c.theta0;  // the lambda_1 estimate was too high (as between passes)
     if (!c.resident) {
         std::vector<sparc_atom> at(c.atoms.size());
         for (size_t i = 0; i < at.size(); ++i) at[i] = c.atoms[i].a;
@@ -205,6 +207,7 @@ int execute(sparc_server *srv, Cluster &c, const Request &r, hipStream_t s, spar
         return st;
     const double *last = theta.data() + (size_t)(passes - 1) * c.ns;
     c.lambda_f = lf[passes - 1];
+    c.theta0 = last[0];
     if (r.ritz) std::memcpy(r.ritz, last, (size_t)c.ns * sizeof(double));
     res.lambda_min = last[0];
     res.lambda_f = c.lambda_f;

@@ -162,3 +162,27 @@ def test_chefsi_argument_errors():
     with pytest.raises(b.SparcError) as ei:
         op.chefsi(X, m, 1, 8.0, a, a0, bb)
     assert ei.value.status == b.SPARC_E_BOUNDS
+
+
+def test_chefsi_a0_above_the_cutoff_is_lowered():
+    """An estimate of lambda_1 above the first pass's Fermi level + 0.1 Ha
+    (as a Lanczos run that missed a low state leaves it): the library lowers
+    a0 to the previous pass's lowest Ritz value, as the oracle does, and the
+    passes match the oracle's in FP64."""
+    b = _b()
+    cl, ns, m, seed = _case("small")
+    _, a, bb = _bounds(cl, seed, ns)
+    a0 = a - 0.05
+    X0 = inputs.orbitals(cl.nd, ns, seed)
+    # 4 electrons: the Fermi level falls in a gap of a few hundred k_B T, where
+    # the occupation constraint fixes it (in a gap wider than ~1400 k_B T the
+    # constraint holds to the last bit over an interval)
+    Xref, rec = oracle.chefsi_passes(cl, X0, m, PASSES, 4.0, a0, a, bb)
+    assert rec[0]["lambda_f"] + 0.1 <= a0 and rec[1]["a0"] == rec[0]["theta"][0]  # the case this tests
+    op = b.Operator(cl)
+    X = torch.from_numpy(X0).cuda()
+    theta, lf, deg = op.chefsi(X, m, PASSES, 4.0, a0, a, bb)
+    for p, r in enumerate(rec):
+        et = np.abs(theta[p] - r["theta"]).max()
+        print(f"a0 lowered: pass {p} a0 {r['a0']:.6f} cutoff {r['cutoff']:.6f} max |dtheta| {et:.2e}", flush=True)
+        assert et <= TOL64 and abs(lf[p] - r["lambda_f"]) <= TOL64

@@ -71,3 +71,29 @@ def test_rotated_block_is_orthonormal_ritz_basis(tiny):
     assert np.abs(G - np.eye(ns)).max() < 1e-10
     Hs = Psi @ oracle.h_apply(cl, Psi).T
     assert np.abs(Hs - np.diag(rec[-1]["theta"])).max() < 1e-9
+
+
+def test_a0_above_the_cutoff_is_lowered(tiny):
+    """A lambda_1 estimate a0 above the first pass's Fermi level + 0.1 Ha
+    (a Lanczos estimate that had not converged): the next pass takes a0 =
+    the lowest Ritz value of the previous pass, and since a0 only scales
+    the filter's output, every pass's Ritz values and Fermi level equal
+    those of the same passes run with the exact lambda_1."""
+    cl, lam = tiny
+    ns, ne, m = 12, 2.0, 16
+    _, a, b = _bounds(cl, lam, ns)
+    X = inputs.orbitals(cl.nd, ns, 6)
+    high = float(lam[6])
+    _, rec = oracle.chefsi_passes(cl, X, m, 3, ne, high, a, b)
+    _, ref = oracle.chefsi_passes(cl, X, m, 3, ne, float(lam[0]), a, b)
+    assert rec[0]["lambda_f"] + 0.1 <= high  # the case this pins
+    assert rec[0]["a0"] == high and rec[1]["a0"] == rec[0]["theta"][0] and rec[2]["a0"] == rec[1]["a0"]
+    assert all(r["a0"] == lam[0] for r in ref)
+    for r, q in zip(rec, ref):
+        # equal to rounding: the low states to the last bits, the damped
+        # ones (above the cutoff) with the filter's rounding amplified by its
+        # damping ratio
+        assert np.abs(r["theta"][:4] - q["theta"][:4]).max() < 1e-12
+        assert np.abs(r["theta"] - q["theta"]).max() < 1e-8
+        assert abs(r["lambda_f"] - q["lambda_f"]) < 1e-12
+    assert abs(rec[-1]["theta"][0] - lam[0]) < 1e-8
