@@ -550,22 +550,23 @@ int sparc_profile_read(int32_t kernel, int64_t *launches, double *total_ms);
 int sparc_profile_reset(void);
 
 /* Override the launch configuration of the vector step kernels (the fused
- * stencil / potential / projector scatter / recurrence pass with the
- * projections of its result) for one dtype: patch extent along z and y
- * (tile_z = 32 with tile_y 16, 32 or 64 for FP32, 8, 16 or 32 for FP64;
- * tile_z = 64 with tile_y 16 or 32 for FP32, 8 or 16 for FP64), the
- * number of x-planes per workgroup (chunk_x <= 0: library choice; rounded up
- * to a multiple of 8) and the column group (col_group <= 0: library choice;
- * that many column blocks of one patch go to consecutive workgroups, so they
- * share V_eff and the projector values in the L2 cache) and the column block
- * (col_block: columns stepped by one workgroup, 1 or 2, sharing the V_eff
- * loads; 0: library choice).  tile_z = tile_y = 0 restores the library's
- * patch choice.  Applies to blocks of every width.  The x split, the column
- * group and the column block never change results; the patch height changes
- * the order in which projections are summed (results then agree to
- * rounding).  Not thread-safe against calls that use the op.
+ * stencil / potential / recurrence pass with the projections of its input
+ * gathered in its last workgroups) for one dtype: patch extent along z and y
+ * (FP32: tile_z = 32 with tile_y 16, 32 or 64; tile_z = 64 with tile_y 16 or
+ * 32; tile_z = 80 with tile_y 32; tile_z = 160 with tile_y 24.  FP64: tile_z
+ * = 32 with tile_y 8, 16 or 32; tile_z = 64 with tile_y 8, 16 or 24), the
+ * number of x-planes per workgroup (chunk_x <= 0: library choice; the x
+ * extent is split into equal chunks of at most chunk_x planes) and the column
+ * group (col_group <= 0: library choice; that many column blocks of one patch
+ * go to consecutive workgroups, so they share V_eff in the L2 cache) and the
+ * column block (col_block: columns stepped by one workgroup, 1 or 2, sharing
+ * the V_eff loads; 2 only on patches of at most 512 threads; 0: library
+ * choice).  tile_z = tile_y = 0 restores the library's patch choice.  Applies
+ * to blocks of every width.  The x split, the column group and the column
+ * block never change results; another patch may change the last bits.  Not
+ * thread-safe against calls that use the op.
  * Errors: SPARC_E_ARG (null op, bad dtype, unsupported tile, col_block
- * outside 0..2). */
+ * outside 0..2, or 2 on a patch of more than 512 threads). */
 int sparc_op_set_launch(sparc_op *op, int32_t dtype, int32_t tile_z, int32_t tile_y, int32_t chunk_x,
                         int32_t col_group, int32_t col_block);
 
