@@ -255,6 +255,28 @@ def test_rayleigh_ritz_sizes(ns):
     assert np.abs(Hs @ Q - Ms @ Q * theta).max() < 1e-8 * max(1.0, np.abs(Hs).max())
 
 
+@pytest.mark.parametrize("n", [(17, 15, 22), (17, 15, 21)], ids=["z-even", "z-odd"])
+def test_rayleigh_ritz_f32_block_grids(n):
+    """FP64 Rayleigh-Ritz of an FP32 block (FP64 H Y on the widened values,
+    FP64 projection) on grids with an even and an odd z extent, with a padded
+    leading dimension: Ritz values and the projected pencil against the
+    oracle fed the same FP32 values (the library applies its FP64 operator to
+    them)."""
+    cl = inputs.make_cluster(n, 0.5, 2, 4, 1, seed=23, min_dist=0.0, margin=2.0)
+    ns = 12
+    Y = inputs.round_to_f32(np.random.default_rng(5).standard_normal((ns, cl.nd)))
+    rt, _, Hs, Ms = oracle.rayleigh_ritz(cl, Y)
+    op = _b().Operator(cl)
+    pad = 2 if n[2] % 2 == 0 else 1
+    big = torch.zeros((ns, cl.nd + pad), dtype=torch.float32, device="cuda")
+    big[:, : cl.nd] = dev(Y, torch.float32)
+    theta, Qt = op.rayleigh_ritz(big[:, : cl.nd])
+    print(f"{n} f32 block RR max |dtheta| {np.abs(theta - rt).max():.2e}")
+    assert np.abs(theta - rt).max() <= 1e-9 * max(1.0, np.abs(rt).max())
+    Q = host(Qt).T
+    assert np.abs(Q.T @ Ms @ Q - np.eye(ns)).max() < 1e-9
+
+
 def test_lanczos_medium_grid():
     c = inputs.MEDIUM
     cl = inputs.case_cluster(c.name)
