@@ -37,6 +37,7 @@ namespace {
 constexpr int kLmax = 6;                           // largest expansion order supported
 constexpr int kNM = (kLmax + 1) * (kLmax + 1);     // moments
 constexpr int kPT = 256;                           // threads per workgroup
+constexpr int kBjStage = 64;                       // largest block (nodes) whose inverse is staged in LDS
 constexpr int kRedMax = 1024;                      // workgroups of the reduction kernels
 constexpr int kChunk = 8;                          // CG iterations enqueued between convergence reads
 constexpr double kFourPi = 12.566370614359172954;  // 4 pi
@@ -296,8 +297,9 @@ __device__ __forceinline__ int bj_shape(const BjGeo &q, int bi, int bj, int bk, 
 // row, so its global accesses are rows of G b2 consecutive nodes (coalesced):
 // thread t owns node (a, b, zz) of the brick, t = (a b1 + b) G b2 + zz.  The
 // residual goes through LDS into block order, thread (slot, row) forms row
-// `row` of M^-1 r for block `slot` (sum over j ascending), and the result goes
-// back through LDS to the brick order for the coalesced store.
+// `row` of M^-1 r for block `slot` (sum over j ascending; the interior
+// blocks' inverse read from LDS), and the result goes back through LDS to the
+// brick order for the coalesced store.
 // UPDATE: alpha = rz_old / pq, x += alpha p, r -= alpha q; both modes:
 // z = M^-1 r per block, p = z (INIT only), partials of r.z and r.r
 template <bool UPDATE>
@@ -310,7 +312,14 @@ __global__ void __launch_bounds__(kPT)
     __shared__ double red[4];
     __shared__ double rs[kPT];
     __shared__ double zs[kPT];
+    // the inverse of the interior block shape (code 0), read by every row of
+    // every interior block, staged once per workgroup (blocks of at most
+    // kBjStage nodes)
+    __shared__ double sM[kBjStage * kBjStage];
     if (UPDATE && state->done) return;
+    const bool staged = q.maxm <= kBjStage;
+    if (staged)
+        for (int e = threadIdx.x; e < q.maxm * q.maxm; e += kPT) sM[e] = minv[e];
     double alpha = 0.0;
     if (UPDATE) alpha = sum_partials(part_rz_old, n_rz_old, red) / sum_partials(part_pq, n_pq, red);
     const int G = kPT / q.maxm;          // blocks per brick
@@ -357,10 +366,16 @@ __global__ void __launch_bounds__(kPT)
             const int code = bj_shape(q, bi, bj, bk0 + cslot, cd);
             const int m = cd[0] * cd[1] * cd[2];
             if (crow < m) {
-                const double *M = minv + (long long)code * q.maxm * q.maxm;
                 const double *rb = rs + cslot * q.maxm;
                 double zv = 0.0;
-                for (int j = 0; j < m; ++j) zv += M[(long long)j * m + crow] * rb[j];
+                if (staged && code == 0) {
+#pragma unroll 8
+                    for (int j = 0; j < m; ++j) zv += sM[j * m + crow] * rb[j];
+                } else {
+                    const double *M = minv + (long long)code * q.maxm * q.maxm;
+#pragma unroll 8
+                    for (int j = 0; j < m; ++j) zv += M[(long long)j * m + crow] * rb[j];
+                }
                 zs[cslot * q.maxm + crow] = zv;
             }
         }
