@@ -158,14 +158,32 @@ struct FStep {
         for (int b = 0; b < B; ++b) {
             const T *L = sh.plane[S][b];
             const V cen = q[b][slot<Q>(R)];
-            // z window: PADZ values on each side of the lane's unit
+            // z window: PADZ values on each side of the lane's unit.  Only
+            // [PADZ - R, PADZ + VZ - 1 + R] is used: the centre unit is the
+            // lane's own (registers), an edge unit of which only an aligned
+            // half is used reads that half
             T w[WU * VZ];
             const T *row = &L[(R + ly) * SZ + VZ * lz];
+            constexpr int WLO = PADZ - R, WHI = PADZ + VZ - 1 + R;
 #pragma unroll
             for (int u = 0; u < WU; ++u) {
-                const V t = *(const V *)&row[u * VZ];
+                const int u0 = u * VZ, u1 = u0 + VZ - 1;
+                const int b0 = u0 > WLO ? u0 : WLO, b1 = u1 < WHI ? u1 : WHI;
+                if (u == ZU) {
 #pragma unroll
-                for (int j = 0; j < VZ; ++j) w[u * VZ + j] = t[j];
+                    for (int j = 0; j < VZ; ++j) w[u0 + j] = cen[j];
+                } else if (b0 == u0 && b1 == u1) {
+                    const V t = *(const V *)&row[u0];
+#pragma unroll
+                    for (int j = 0; j < VZ; ++j) w[u0 + j] = t[j];
+                } else if (b0 <= b1) {
+                    constexpr int H = VZ / 2;
+                    const int h0 = (b0 - u0) / H * H;  // the aligned half holding b0 .. b1
+                    typedef T VH __attribute__((ext_vector_type(VZ / 2)));
+                    const VH t = *(const VH *)&row[u0 + h0];
+#pragma unroll
+                    for (int j = 0; j < H; ++j) w[u0 + h0 + j] = t[j];
+                }
             }
             T acc[VZ];
 #pragma unroll
