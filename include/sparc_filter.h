@@ -202,9 +202,9 @@ size_t sparc_rr_workspace_bytes(const sparc_op *op, int32_t dtype, int32_t ns);
  * theta: host array of ns Ritz values, ascending.  evec: optional device FP64
  * ns x ns column-major array receiving the M_s-orthonormal eigenvectors (the
  * rotation matrix of Eq. OrbitalTransformation).  Synchronous.
- * Errors: SPARC_E_ARG, SPARC_E_SHAPE, SPARC_E_WORKSPACE, SPARC_E_HIP,
- * SPARC_E_BREAKDOWN (M_s not numerically positive definite: the filtered
- * columns are linearly dependent to working precision). */
+ * Errors: SPARC_E_ARG, SPARC_E_SHAPE (also 8 ldy + nd >= 2^32), SPARC_E_WORKSPACE,
+ * SPARC_E_HIP, SPARC_E_BREAKDOWN (M_s not numerically positive definite: the
+ * filtered columns are linearly dependent to working precision). */
 int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_t ldy, int32_t ns,
                         double *theta, double *evec, void *ws, size_t ws_bytes, void *stream);
 

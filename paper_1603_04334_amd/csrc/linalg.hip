@@ -373,7 +373,19 @@ __global__ void f64_to_f32_dense(const double *src, float *dst, long long n)
 // panel of a chunk comes from HBM about once.
 
 constexpr int kRrTile = 64;
-constexpr int kRrK = 32;
+constexpr int kRrK = 32;  // chunks of the contraction are multiples of this
+
+// Staged slice geometry per block type.  FP32 panels stay FP32 in LDS (widened
+// when read as MFMA operands).  Row strides put the 16 rows x 4 points of one
+// operand read in distinct banks.
+template <typename TY>
+struct RrSlice {
+    static constexpr int K = kRrK;                              // points per slice
+    static constexpr int SA = sizeof(TY) == 4 ? K + 4 : K + 1;  // Y panel row stride (elements)
+    static constexpr int SH = K + 1;                            // HY panel row stride (doubles)
+    static constexpr int CPP = 256 / K;                         // columns staged per pass
+    static constexpr int NP = kRrTile / CPP;                    // passes per slice
+};
 
 __device__ inline void mfma_f64(double a, double b, double (&acc)[4])
 {
@@ -387,13 +399,15 @@ __device__ inline void mfma_f64(double a, double b, double (&acc)[4])
 }
 
 template <typename TY>
-__global__ void __launch_bounds__(256) rr_project_kernel(const TY *__restrict__ Y, long long ldy,
+__global__ void __launch_bounds__(256, 2) rr_project_kernel(const TY *__restrict__ Y, long long ldy,
                                                           const double *__restrict__ HY, long long ldh, long long nd,
                                                           int ns, long long kchunk, double *__restrict__ partial)
 {
-    __shared__ double sA[kRrTile][kRrK + 1];  // Y columns of the row tile, [col][k]
-    __shared__ double sB[kRrTile][kRrK + 1];  // Y columns of the column tile
-    __shared__ double sH[kRrTile][kRrK + 1];  // HY columns of the column tile
+    using G = RrSlice<TY>;
+    constexpr int KS = G::K;
+    __shared__ TY sA[kRrTile][G::SA];         // Y columns of the row tile, [col][k]
+    __shared__ TY sB[kRrTile][G::SA];         // Y columns of the column tile
+    __shared__ double sH[kRrTile][G::SH];     // HY columns of the column tile
     // (chunk, tile pair) from the XCD-contiguous workgroup order; tile pair
     // (ti <= tj) numbered in row order: both matrices are symmetric, so only
     // the upper tiles are formed
@@ -414,47 +428,56 @@ __global__ void __launch_bounds__(256) rr_project_kernel(const TY *__restrict__ 
     const int lane = tid & 63, wave = tid >> 6;
     const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;  // wave's quarter
     const int li = lane & 15, lk = lane >> 4;
-    const int kk = tid & 31;
+    const int kk = tid % KS;
     double accM[2][2][4] = {}, accH[2][2][4] = {};
-    TY ra[8], rb[8];  // raw values, widened when staged (keeps the loads in flight)
-    double rh[8];
+    TY ra[G::NP], rb[G::NP];  // raw values of the next slice (keeps the loads in flight)
+    double rh[G::NP];
 
-    // thread -> (column c = 8*pass + tid/32, point kk = tid%32 of the slice).
+    // thread -> (column c = CPP*pass + tid/KS, point kk = tid%KS of the slice).
     // On a diagonal tile pair both Y panels are the same columns: read and
     // stage them once.
     const bool diag = ti == tj;
+    // Addresses: a workgroup-uniform 64-bit base per pass (column CPP*pass of
+    // the tile) plus a 32-bit lane offset (its column within the pass times
+    // the leading dimension, plus the point), so no 64-bit lane addresses
+    // stay live across the slice loop.
+    const int cl = tid / KS;
     auto fetch = [&](long long kb) {
         const long long k = kb + kk;
         const bool kin = k < k1;
+        const unsigned oy = (unsigned)(cl * ldy + k), oh = (unsigned)(cl * ldh + k);
 #pragma unroll
-        for (int pass = 0; pass < 8; ++pass) {
-            const int c = pass * 8 + (tid >> 5);
-            const int ca = ti * kRrTile + c, cb = tj * kRrTile + c;
-            ra[pass] = (kin && ca < ns) ? Y[(long long)ca * ldy + k] : TY(0);
-            if (!diag) rb[pass] = (kin && cb < ns) ? Y[(long long)cb * ldy + k] : TY(0);
-            rh[pass] = (kin && cb < ns) ? HY[(long long)cb * ldh + k] : 0.0;
+        for (int pass = 0; pass < G::NP; ++pass) {
+            const int c0 = pass * G::CPP;
+            const int ca = ti * kRrTile + c0 + cl, cb = tj * kRrTile + c0 + cl;
+            const TY *ya = Y + (long long)(ti * kRrTile + c0) * ldy;
+            const TY *yb = Y + (long long)(tj * kRrTile + c0) * ldy;
+            const double *hb = HY + (long long)(tj * kRrTile + c0) * ldh;
+            ra[pass] = (kin && ca < ns) ? ya[oy] : TY(0);
+            if (!diag) rb[pass] = (kin && cb < ns) ? yb[oy] : TY(0);
+            rh[pass] = (kin && cb < ns) ? hb[oh] : 0.0;
         }
     };
     fetch(k0);
-    for (long long kb = k0; kb < k1; kb += kRrK) {
+    for (long long kb = k0; kb < k1; kb += KS) {
         __syncthreads();
 #pragma unroll
-        for (int pass = 0; pass < 8; ++pass) {
-            const int c = pass * 8 + (tid >> 5);
-            sA[c][kk] = (double)ra[pass];
-            if (!diag) sB[c][kk] = (double)rb[pass];
+        for (int pass = 0; pass < G::NP; ++pass) {
+            const int c = pass * G::CPP + tid / KS;
+            sA[c][kk] = ra[pass];
+            if (!diag) sB[c][kk] = rb[pass];
             sH[c][kk] = rh[pass];
         }
         __syncthreads();
-        if (kb + kRrK < k1) fetch(kb + kRrK);
-        const double(*SB)[kRrK + 1] = diag ? sA : sB;
+        if (kb + KS < k1) fetch(kb + KS);
+        const TY(*SB)[G::SA] = diag ? sA : sB;
 #pragma unroll
-        for (int ks = 0; ks < kRrK; ks += 4) {
+        for (int ks = 0; ks < KS; ks += 4) {
             double a[2], b[2], h[2];
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
-                a[u] = sA[wi + 16 * u + li][ks + lk];
-                b[u] = SB[wj + 16 * u + li][ks + lk];
+                a[u] = (double)sA[wi + 16 * u + li][ks + lk];
+                b[u] = (double)SB[wj + 16 * u + li][ks + lk];
                 h[u] = sH[wj + 16 * u + li][ks + lk];
             }
 #pragma unroll
@@ -466,7 +489,7 @@ __global__ void __launch_bounds__(256) rr_project_kernel(const TY *__restrict__ 
                 }
         }
     }
-    // partial[(chunk*2 + which)][col][row] of the full ns x ns matrices
+// partial[(chunk*2 + which)][col][row] of the full ns x ns matrices
     const long long mat = (long long)ns * ns;
     double *pm = partial + (long long)chunk * 2 * mat;
     double *ph = pm + mat;
@@ -869,6 +892,10 @@ int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_
     if (!op || !Y || !theta) return fail(SPARC_E_ARG, "null argument");
     if (dtype != SPARC_F64 && dtype != SPARC_F32) return fail(SPARC_E_ARG, "bad dtype");
     if (ns < 1 || ldy < op->nd) return fail(SPARC_E_SHAPE, "ns < 1 or ldy < N_d");
+    // the projection addresses a lane's point by a 32-bit element offset from
+    // its pass's first column
+    if ((long long)RrSlice<double>::CPP * ldy + op->nd >= (1LL << 32))
+        return fail(SPARC_E_SHAPE, "ldy too large for the projection kernel");
     const size_t need = sparc_rr_workspace_bytes(op, dtype, ns);
     if (!ws || ws_bytes < need) return fail(SPARC_E_WORKSPACE, "workspace too small");
     hipStream_t s = (hipStream_t)stream;
