@@ -237,6 +237,14 @@ def test_argument_errors(small):
     assert st == binding.SPARC_E_SHAPE
     st = lib.sparc_h_apply(op.handle, 7, Xd.data_ptr(), cl.nd, Y.data_ptr(), cl.nd, c.ns, ws.data_ptr(), ws.numel(), None)
     assert st == binding.SPARC_E_ARG
+    # the projection addresses points by 32-bit offsets from a pass's first
+    # column: a leading dimension with 8 ldy + nd >= 2^32 is refused before
+    # anything is read
+    theta = np.zeros(c.ns)
+    for ldy, want in ((cl.nd - 1, binding.SPARC_E_SHAPE), ((1 << 29), binding.SPARC_E_SHAPE)):
+        st = lib.sparc_rayleigh_ritz(op.handle, 0, Xd.data_ptr(), ldy, c.ns, theta.ctypes.data_as(binding._dp), None,
+                                     ws.data_ptr(), ws.numel(), None)
+        assert st == want, ldy
 
 
 @pytest.mark.parametrize("ns", [1, 7, 33, 64, 70])
