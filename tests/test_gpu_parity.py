@@ -261,6 +261,12 @@ def test_rayleigh_ritz_sizes(ns):
     # M-orthonormal eigenvectors of the oracle's projected pencil
     assert np.abs(Q.T @ Ms @ Q - np.eye(ns)).max() < 1e-9
     assert np.abs(Hs @ Q - Ms @ Q * theta).max() < 1e-8 * max(1.0, np.abs(Hs).max())
+    # a padded leading dimension (even, so H Y takes the same vector launch)
+    # changes only the addresses: the same Ritz values and vectors bit for bit
+    big = torch.zeros((ns, cl.nd + 38), dtype=torch.float64, device="cuda")
+    big[:, : cl.nd] = dev(Y)
+    theta_p, Qt_p = op.rayleigh_ritz(big[:, : cl.nd])
+    assert np.array_equal(theta_p, theta) and torch.equal(Qt_p, Qt)
 
 
 @pytest.mark.parametrize("n", [(17, 15, 22), (17, 15, 21)], ids=["z-even", "z-odd"])
