@@ -489,7 +489,7 @@ __global__ void __launch_bounds__(256, 2) rr_project_kernel(const TY *__restrict
                 }
         }
     }
-// partial[(chunk*2 + which)][col][row] of the full ns x ns matrices
+    // partial[(chunk*2 + which)][col][row] of the full ns x ns matrices
     const long long mat = (long long)ns * ns;
     double *pm = partial + (long long)chunk * 2 * mat;
     double *ph = pm + mat;
