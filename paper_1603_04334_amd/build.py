@@ -43,7 +43,8 @@ def build(verbose: bool = False, jobs: int = 16) -> str:
     _wait(procs)
     tmp = LIB + ".tmp%d" % os.getpid()
     link = [os.path.join(ROCM, "bin", "hipcc"), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
-            f"-L{ROCM}/lib", "-lrocsolver", "-lrocblas", f"-Wl,-rpath,{ROCM}/lib"]
+            f"-L{ROCM}/lib", "-lrocsolver", "-lrocblas", "-lrocprofiler-sdk-roctx",
+            f"-Wl,-rpath,{ROCM}/lib"]
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.check_call(link)

@@ -5,6 +5,8 @@
 #include <cstring>
 #include <new>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "internal.hpp"
 
 namespace sparc {
@@ -35,6 +37,9 @@ constexpr int kProfKernels = 8;
 int64_t g_prof_count[kProfKernels] = {};
 double g_prof_ms[kProfKernels] = {};
 }  // namespace
+
+TraceRange::TraceRange(const char *name) { roctxRangePushA(name); }
+TraceRange::~TraceRange() { roctxRangePop(); }
 
 ProfScope::ProfScope(int k, hipStream_t s) : kernel(k), stream(s)
 {
@@ -469,6 +474,7 @@ int sparc_h_apply(const sparc_op *op, int32_t dtype, const void *X, int64_t ldx,
     StepCoef c{1.0, 0.0, 0.0, 0};
     const FLaunch V = choose_vec_launch(op, dtype, ns, {ldx, ldy});
     StepLaunch L = choose_step_launch(op, dtype, ns);
+    TraceRange trace("sparc_h_apply");
     return launch_h_step(op, dtype, X, ldx, nullptr, 0, Y, ldy, ns, ws, c, L, s, &V);
 }
 
@@ -488,6 +494,7 @@ int sparc_cheb_filter(const sparc_op *op, int32_t dtype, const void *X, int64_t 
     if (overlaps(X, bx, Y, by) || overlaps(X, bx, ws, need) || overlaps(Y, by, ws, need))
         return fail(SPARC_E_ALIAS, "X, Y and the workspace must not overlap");
 
+    TraceRange trace("sparc_cheb_filter");
     hipStream_t s = (hipStream_t)stream;
     char *G = (char *)ws;
     char *W = G + gather_bytes(op, dtype, ns);
@@ -510,7 +517,10 @@ int sparc_cheb_filter(const sparc_op *op, int32_t dtype, const void *X, int64_t 
 
     // Y_1 = (sigma_1/e)(H - cI) X
     StepCoef c1{sigma1 / e, 0.0, c, 0};
-    if ((st = launch_h_step(op, dtype, X, ldx, nullptr, 0, P, ldP, ns, G, c1, L, s, &V))) return st;
+    {
+        TraceRange step("filter step");
+        if ((st = launch_h_step(op, dtype, X, ldx, nullptr, 0, P, ldP, ns, G, c1, L, s, &V))) return st;
+    }
 
     double sigma = sigma1;
     for (int k = 1; k < m; ++k) {
@@ -522,6 +532,7 @@ int sparc_cheb_filter(const sparc_op *op, int32_t dtype, const void *X, int64_t 
         void *out = ((k + 1) & 1) ? P : Q;
         const int64_t ldo = ((k + 1) & 1) ? ldP : ldQ;
         StepCoef ck{2.0 * sigma_next / e, sigma * sigma_next, c, 1};
+        TraceRange step("filter step");
         if ((st = launch_h_step(op, dtype, yk, ldk, yprev, ldp, out, ldo, ns, G, ck, L, s, &V))) return st;
         sigma = sigma_next;
     }

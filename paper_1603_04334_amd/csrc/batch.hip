@@ -622,6 +622,7 @@ int sparc_batch_create(const sparc_batch_job *jobs, int32_t njobs, int32_t mode,
 int sparc_batch_run(sparc_batch *b, void *stream)
 {
     if (!b) return fail(SPARC_E_ARG, "batch is NULL");
+    TraceRange trace("sparc_batch_run");
     hipStream_t s = (hipStream_t)stream;
     if (b->mode == 5) {
         // the batch's streams start after the caller's stream's earlier work

@@ -67,6 +67,7 @@ int chefsi_run(const sparc_op *op, int dtype, void *X, int64_t ldx, int ns, int 
     double cut = a, lf = 0.0;
     int st;
     for (int p = 0; p < passes; ++p) {
+        TraceRange pass("chefsi pass");
         if (p > 0) {
             cut = lf + kCutoffShift;
             if (cut <= a0) a0 = th[0];  // th: the previous pass's Ritz values

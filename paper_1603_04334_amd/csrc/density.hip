@@ -246,6 +246,7 @@ extern "C" int sparc_density(int32_t dtype, const void *psi, int64_t ld, int64_t
     const char *r0 = (const char *)rho, *r1 = r0 + (size_t)nd * sizeof(double);
     if (p0 < r1 && r0 < p1) return fail(SPARC_E_ALIAS, "rho overlaps the orbital block");
     const double scale = 2.0 / (h * h * h);
+    TraceRange trace("sparc_density");
     hipStream_t s = (hipStream_t)stream;
     return dtype == SPARC_F64 ? launch_density((const double *)psi, ld, nd, ns, occ, scale, rho, s)
                               : launch_density((const float *)psi, ld, nd, ns, occ, scale, rho, s);

@@ -217,6 +217,7 @@ extern "C" int sparc_nonlocal_force(const sparc_op *op, int32_t dtype, const voi
             if (st) return st;
         }
     }
+    TraceRange trace("sparc_nonlocal_force");
     hipStream_t s = (hipStream_t)stream;
     const dim3 grid(4 * op->natoms, (ns + 15) / 16, kGatherSplit);
     const double h3 = op->h * op->h * op->h;

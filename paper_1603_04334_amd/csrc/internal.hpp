@@ -240,6 +240,16 @@ int chefsi_run(const sparc_op *op, int dtype, void *X, int64_t ldx, int ns, int 
                double &a0, double a, double b, const ChefsiBuffers &B, double *theta, double *lambda_f,
                int32_t *degrees, double *rho, hipStream_t s, int *halvings);
 
+// roctx range over the host side of an entry point or a step of it, for
+// timelines that show the library's phases beside its kernels (rocprofv3
+// --marker-trace); without a tool that records markers it costs a call
+struct TraceRange {
+    explicit TraceRange(const char *name);
+    ~TraceRange();
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
+
 // profiling hooks (no-ops unless enabled)
 struct ProfScope {
     int kernel;

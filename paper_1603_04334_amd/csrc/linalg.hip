@@ -778,6 +778,7 @@ int sparc_lanczos(const sparc_op *op, int32_t k, const double *v0, double *alpha
     if (k < 1 || k > op->nd) return fail(SPARC_E_ARG, "need 1 <= k <= N_d");
     const size_t need = sparc_lanczos_workspace_bytes(op, k);
     if (!ws || ws_bytes < need) return fail(SPARC_E_WORKSPACE, "workspace too small");
+    TraceRange trace("sparc_lanczos");
     hipStream_t s = (hipStream_t)stream;
     const long long n = op->nd;
     char *p = (char *)ws;
@@ -898,6 +899,7 @@ int sparc_rayleigh_ritz(const sparc_op *op, int32_t dtype, const void *Y, int64_
         return fail(SPARC_E_SHAPE, "ldy too large for the projection kernel");
     const size_t need = sparc_rr_workspace_bytes(op, dtype, ns);
     if (!ws || ws_bytes < need) return fail(SPARC_E_WORKSPACE, "workspace too small");
+    TraceRange trace("sparc_rayleigh_ritz");
     hipStream_t s = (hipStream_t)stream;
     const long long nd = op->nd;
     char *p = (char *)ws;
@@ -1041,6 +1043,7 @@ int sparc_rotate(int32_t dtype, const void *Y, int64_t ldy, int64_t nd, int32_t 
     const char *pw = (const char *)ws;
     if ((pw < pa + by && pa < pw + need) || (pw < pb + bo && pb < pw + need))
         return fail(SPARC_E_ALIAS, "workspace overlaps Y or out");
+    TraceRange trace("sparc_rotate");
     hipStream_t s = (hipStream_t)stream;
     const unsigned gx = (unsigned)((nd + 255) / 256);
     const int ldq = rot_ldq(ns);

@@ -697,6 +697,7 @@ extern "C" int sparc_poisson_solve(sparc_poisson *P, const double *charge, doubl
     const char *w0 = (const char *)ws, *w1 = w0 + W.total;
     if ((c0 < f1 && f0 < c1) || (w0 < f1 && f0 < w1) || (w0 < c1 && c0 < w1))
         return fail(SPARC_E_ALIAS, "charge, phi and the workspace must not overlap");
+    TraceRange trace("sparc_poisson_solve");
     hipStream_t s = (hipStream_t)stream;
     const int nvec = P->nred;
     ProfScope prof(6, s);

@@ -161,6 +161,7 @@ void free_device(Cluster &c, hipStream_t s)
 // runs one request on stream s; returns a status
 int execute(sparc_server *srv, Cluster &c, const Request &r, hipStream_t s, sparc_job_result &res)
 {
+    TraceRange trace("serve request");
     int st;
     int passes = 1;
     double cut = c.lambda_f + 0.1;  // Sec. 4: previous Fermi level + 0.1 Ha
