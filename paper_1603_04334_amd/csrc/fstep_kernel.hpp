@@ -73,6 +73,10 @@ struct FStep {
     static constexpr int NH = (NHALO + NT - 1) / NT;
     static constexpr int WU = 2 * ZU + 1;  // units of a lane's z window
     static_assert(NT % 64 == 0, "whole waves");
+    // the z window reads an edge unit whole or one aligned half of it: the
+    // used range must start and end on half-unit boundaries
+    static_assert(VZ == 1 || ((PADZ - R) % (VZ / 2) == 0 && (PADZ + VZ + R) % (VZ / 2) == 0),
+                  "z window edges must fall on half units");
     static_assert(B == 1 || B == 2, "one or two columns per workgroup");
 
     struct Shared {
