@@ -269,6 +269,23 @@ def test_rayleigh_ritz_sizes(ns):
     assert np.array_equal(theta_p, theta) and torch.equal(Qt_p, Qt)
 
 
+@pytest.mark.parametrize("ns", [1, 7, 64, 70, 130])
+def test_rayleigh_ritz_f32_block_sizes(ns):
+    """FP32 blocks of one tile, a ragged tile, and 2-3 tiles (diagonal and
+    off-diagonal tile pairs, a ragged last tile) through the FP64
+    Rayleigh-Ritz: Ritz values and the projected pencil against the oracle
+    fed the same FP32 values."""
+    cl = inputs.make_cluster(16, 0.5, 2, 4, 1, seed=22, min_dist=0.0, margin=3.0)
+    Y = inputs.round_to_f32(np.random.default_rng(100 + ns).standard_normal((ns, cl.nd)))
+    rt, _, Hs, Ms = oracle.rayleigh_ritz(cl, Y)
+    op = _b().Operator(cl)
+    theta, Qt = op.rayleigh_ritz(dev(Y, torch.float32))
+    assert np.abs(theta - rt).max() <= 1e-9 * max(1.0, np.abs(rt).max())
+    Q = host(Qt).T
+    assert np.abs(Q.T @ Ms @ Q - np.eye(ns)).max() < 1e-9
+    assert np.abs(Hs @ Q - Ms @ Q * theta).max() < 1e-8 * max(1.0, np.abs(Hs).max())
+
+
 @pytest.mark.parametrize("n", [(17, 15, 22), (17, 15, 21)], ids=["z-even", "z-odd"])
 def test_rayleigh_ritz_f32_block_grids(n):
     """FP64 Rayleigh-Ritz of an FP32 block (FP64 H Y on the widened values,
